@@ -1,0 +1,216 @@
+/*
+ * nbody.h -- C ABI of the MI355X direct N-body force library.
+ *
+ * The library evaluates, by direct summation on the GPU, the Plummer-softened
+ * gravitational acceleration, its time derivative (jerk) and the potential of
+ * a set of i-particles due to a set of j-particles (Eq. 1 of the paper, with
+ * the softening of Section 3.3 and the jerk and potential of Section 3), and
+ * drives a fourth-order Hermite predictor-corrector with block time steps
+ * (Section 3 and 3.1) whose prediction, correction and block selection also
+ * run on the GPU.
+ *
+ * Conventions (apply to every function):
+ *  - Every function returns an int status: NBODY_OK (0) or a negative
+ *    NBODY_ERR_* code.  nbody_last_error(ctx) gives a human-readable detail
+ *    for the last failing call on that context.  The library never aborts
+ *    and never prints.
+ *  - Array arguments are DEVICE pointers unless stated otherwise: contiguous
+ *    float64 structure-of-arrays rows (one pointer per component), 8-byte
+ *    aligned, owned by the caller.  The library never frees or keeps them
+ *    after a call returns.
+ *  - Work is enqueued asynchronously on the given HIP stream (NULL = the
+ *    default stream); outputs are ready when the stream reaches that point.
+ *    Argument errors are reported synchronously, before anything is
+ *    launched; a device fault surfaces at a later call or at nbody_sync.
+ *  - Scratch memory (packed particle copies, split partial sums, block
+ *    lists) belongs to the context, grows on demand and is kept until
+ *    nbody_destroy; nbody_reserve pre-sizes it outside timed regions.
+ *  - A context is not thread-safe: use one per host thread.  Two calls on
+ *    one context that overlap in time on different streams race on the
+ *    context's scratch memory.
+ *  - Particle counts are int64 arguments but must not exceed 2^31 - 1
+ *    (kernels index with int32).
+ *  - G and eps are float64; eps must be finite and >= 0.  eps == 0 selects
+ *    the unsoftened form, in which a pair at zero separation contributes
+ *    nothing (the zero-softening check of Section 3.3).
+ *  - Outputs are overwritten, never accumulated into.
+ */
+#ifndef NBODY_H
+#define NBODY_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define NBODY_ABI_VERSION 1
+
+enum {
+    NBODY_OK = 0,
+    NBODY_ERR_ARG = -1,          /* invalid argument (NULL, size, eps, alignment) */
+    NBODY_ERR_NOMEM = -2,        /* device or host allocation failed */
+    NBODY_ERR_DEVICE = -3,       /* HIP runtime error (launch, copy, fault) */
+    NBODY_ERR_UNSUPPORTED = -4,  /* valid request this build does not serve */
+    NBODY_ERR_STATE = -5         /* object used out of order */
+};
+
+/* Arithmetic of the pairwise loop.
+ *  NBODY_PREC_FP32: positions and velocities rounded to float32 (the 7
+ *    input floats per particle of Section 3.1), float32 pair arithmetic,
+ *    float32 accumulation over all j.
+ *  NBODY_PREC_DS_COMP: positions as double-single (hi = fl32(x),
+ *    lo = fl32(x - hi)); the relative coordinate is formed as
+ *    (x_j,hi - x_i,hi) + (x_j,lo - x_i,lo); float32 pair arithmetic; float32
+ *    partial sums per j-tile folded into a two-sum (hi, lo) accumulator. */
+typedef enum { NBODY_PREC_FP32 = 0, NBODY_PREC_DS_COMP = 1 } nbody_prec;
+
+typedef struct nbody_ctx nbody_ctx;
+
+/* Particle source: device float64 rows of length n.  m may be NULL where a
+ * function says masses are unused (the i side of nbody_force). */
+typedef struct {
+    const double *x, *y, *z, *vx, *vy, *vz, *m;
+} nbody_src;
+
+/* Force output: device float64 rows of length n_i. */
+typedef struct {
+    double *ax, *ay, *az, *jx, *jy, *jz, *pot;
+} nbody_out;
+
+/* Launch shape of the pairwise kernel (also the autotuner's search space).
+ *  tile_j: j-particles staged in LDS per tile, one of 64, 128, 256.
+ *  ipt:    i-particles held in registers per lane, one of 1, 2, 4.
+ *  wg:     work-group size in lanes, one of 128, 256.
+ *  split:  number of j-ranges the j set is cut into (>= 1; 0 = choose
+ *          from the shape); partial sums are reduced in float64 in fixed
+ *          order (Section 3.2). */
+typedef struct {
+    int tile_j, ipt, wg, split;
+} nbody_tile;
+
+/* ---- context ------------------------------------------------------------ */
+
+/* Create a context on HIP device `device` (the caller's current device is
+ * restored).  tune_cache_path: JSON file the autotuner reads and writes, or
+ * NULL for $NBODY_TUNE_CACHE (unset: no persistent cache).  On failure *ctx
+ * is set to NULL and the code is returned (details cannot be queried). */
+int nbody_create(nbody_ctx **ctx, int device, const char *tune_cache_path);
+
+/* Release the context and all of its device memory.  NULL is accepted. */
+int nbody_destroy(nbody_ctx *ctx);
+
+/* Pre-size scratch for up to max_i i-particles against max_j j-particles. */
+int nbody_reserve(nbody_ctx *ctx, int64_t max_i, int64_t max_j);
+
+/* Wait for all work on `stream`; reports deferred device errors. */
+int nbody_sync(nbody_ctx *ctx, hipStream_t stream);
+
+/* Text of the last error on this context ("" if none).  Owned by ctx. */
+const char *nbody_last_error(const nbody_ctx *ctx);
+
+/* NBODY_ABI_VERSION of the loaded library. */
+int nbody_abi_version(void);
+
+/* Force the launch shape used for `prec` (all fields > 0 except split,
+ * which may be 0), or clear the override when t is NULL. */
+int nbody_set_tile(nbody_ctx *ctx, nbody_prec prec, const nbody_tile *t);
+
+/* The launch shape the next nbody_force call would use for this shape. */
+int nbody_get_tile(nbody_ctx *ctx, nbody_prec prec, int64_t n_i, int64_t n_j, nbody_tile *t);
+
+/* ---- force (Eq. 1, Section 3) -------------------------------------------- */
+
+/* Acceleration, jerk and potential of n_i i-particles due to n_j
+ * j-particles (Eq. 1 with Plummer softening, Section 3.3; jerk and
+ * potential, Section 3):
+ *   a_i    =  G sum_j m_j r / s^(3/2)
+ *   jerk_i =  G sum_j m_j (u / s^(3/2) - 3 (r.u) r / s^(5/2))
+ *   pot_i  = -G sum_j m_j / s^(1/2)
+ * with r = x_j - x_i, u = v_j - v_i, s = |r|^2 + eps^2.
+ * i_self: device int32[n_i] giving, for each i, the j index of that same
+ * particle (excluded from the sums) or -1; NULL excludes nothing.  The
+ * kernel visits every j, including j = i_self[i]; that pair contributes
+ * exactly zero to a and jerk because its rows are bit-identical, and its
+ * potential term is removed after the loop (Section 3.1).  The caller must
+ * therefore pass, for a self pair, an i row equal to the j row.
+ * I.m is unused.  Returns NBODY_ERR_ARG for NULL rows, n_i < 0, n_j < 0,
+ * counts above 2^31 - 1, non-finite G or eps, eps < 0. */
+int nbody_force(nbody_ctx *ctx, hipStream_t stream, nbody_prec prec, double G, double eps,
+                int64_t n_i, nbody_src I, const int32_t *i_self,
+                int64_t n_j, nbody_src J, nbody_out out);
+
+/* ---- active-block selection (Section 3.1) ---------------------------------- */
+
+/* Block time steps: with integer times t[k] and steps dt[k] (device int64,
+ * ticks of 2^-20 time units), t_next = min_k (t[k] + dt[k]) and the active
+ * block is { k : t[k] + dt[k] == t_next } in ascending k.  Writes
+ * idx[0 .. n_act-1] (device int32[n]); *n_act and *t_next are HOST
+ * pointers and the call synchronises `stream`.  Pure integer work: the
+ * result is bit-exact.  n == 0 gives n_act = 0. */
+int nbody_select_active(nbody_ctx *ctx, hipStream_t stream, int64_t n, const int64_t *t,
+                        const int64_t *dt, int32_t *idx, int64_t *n_act, int64_t *t_next);
+
+/* ---- Hermite block-step driver (Section 3, 3.1) ----------------------------- */
+
+typedef struct nbody_hermite nbody_hermite;
+
+/* Options.  eta: Aarseth accuracy parameter; eta_start: first step
+ * eta_start |a| / |jerk|; dt levels 2^dt_min_log2 .. 2^dt_max_log2 time
+ * units (each in [-20, 0]); shared_dt_log2 != 0 gives every particle the
+ * fixed step 2^shared_dt_log2 (all particles active every step). */
+typedef struct {
+    double G, eps, eta, eta_start;
+    int dt_min_log2, dt_max_log2;
+    int shared_dt_log2;
+    nbody_prec prec;
+} nbody_hermite_opts;
+
+typedef struct {
+    int64_t steps;        /* block steps taken */
+    int64_t sum_active;   /* sum over steps of the block size */
+    int64_t t_ticks;      /* current block time (ticks) */
+} nbody_hermite_stats;
+
+/* Allocate device state for n particles (all arrays library-owned). */
+int nbody_hermite_create(nbody_ctx *ctx, nbody_hermite **h, int64_t n,
+                         const nbody_hermite_opts *opts);
+int nbody_hermite_destroy(nbody_hermite *h);
+
+/* Load positions, velocities, masses (device rows of length n, copied) at
+ * time 0; evaluate a and jerk of every particle and choose first steps. */
+int nbody_hermite_set_state(nbody_hermite *h, hipStream_t stream, nbody_src P);
+
+/* Copy the current state out (device rows of length n; any may be NULL):
+ * x, v (as P's layout), a, jerk, t and dt in ticks (int64 rows). */
+int nbody_hermite_get_state(nbody_hermite *h, hipStream_t stream, nbody_src P_out_as_mutable,
+                            double *ax, double *ay, double *az, double *jx, double *jy,
+                            double *jz, int64_t *t, int64_t *dt);
+
+/* One block step: select, predict all, evaluate the block, correct, new
+ * steps.  *n_active and *t_ticks (HOST, may be NULL) receive the block size
+ * and the new block time.  Synchronises `stream` once (block size). */
+int nbody_hermite_step(nbody_hermite *h, hipStream_t stream, int64_t *n_active, int64_t *t_ticks);
+
+/* Block steps until the next block time would exceed t_end_ticks. */
+int nbody_hermite_advance(nbody_hermite *h, hipStream_t stream, int64_t t_end_ticks,
+                          nbody_hermite_stats *stats);
+
+/* Total kinetic and potential energy (Eq. 2) at the current state, with
+ * every particle predicted to the latest block time (HOST outputs;
+ * synchronises `stream`). */
+int nbody_hermite_energy(nbody_hermite *h, hipStream_t stream, double *ekin, double *epot);
+
+/* Save / restore the complete integrator state to / from a host buffer of
+ * nbody_hermite_state_bytes(h) bytes (checkpoint and resume; a restored
+ * run continues bit-identically). */
+int64_t nbody_hermite_state_bytes(const nbody_hermite *h);
+int nbody_hermite_save(nbody_hermite *h, hipStream_t stream, void *host_buf);
+int nbody_hermite_load(nbody_hermite *h, hipStream_t stream, const void *host_buf);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NBODY_H */

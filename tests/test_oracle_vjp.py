@@ -1,0 +1,110 @@
+"""Pins of the oracle's force adjoint (vector-Jacobian product) against
+finite differences, symmetry identities and homogeneity (Euler) identities.
+None of them re-derives the adjoint formula."""
+import numpy as np
+import pytest
+
+import oracle
+
+
+def system(n, seed):
+    g = np.random.default_rng(seed)
+    return g.normal(0, 1, (3, n)), g.normal(0, 0.5, (3, n)), g.uniform(0.5, 1.5, n) / n
+
+
+def loss(x, v, m, eps, ga, gj, gp, xi=None, vi=None, iself=None):
+    xi = x if xi is None else xi
+    vi = v if vi is None else vi
+    a, j, p = oracle.force(xi, vi, x, v, m, eps, iself=iself)
+    return (ga * a).sum() + (gj * j).sum() + (gp * p).sum()
+
+
+@pytest.mark.parametrize("eps", [0.0, 0.05])
+def test_vjp_directional_derivatives(eps):
+    # <cotangent, directional FD> = <gradient, direction> for x, v and m.
+    n = 24
+    x, v, m = system(n, 1)
+    g = np.random.default_rng(2)
+    ga, gj, gp = g.normal(size=(3, n)), g.normal(size=(3, n)), g.normal(size=n)
+    iself = np.arange(n)
+    gxi, gvi, gxj, gvj, gmj = oracle.force_vjp(x, v, x, v, m, eps, ga, gj, gp, iself=iself)
+    gx, gv = gxi + gxj, gvi + gvj
+    h = 1e-6
+    for name, grad in (("x", gx), ("v", gv), ("m", gmj)):
+        d = g.normal(size=grad.shape)
+        def f(t):
+            xx, vv, mm = x.copy(), v.copy(), m.copy()
+            if name == "x":
+                xx += t * d
+            elif name == "v":
+                vv += t * d
+            else:
+                mm += t * d
+            return loss(xx, vv, mm, eps, ga, gj, gp, iself=iself)
+        fd = (f(h) - f(-h)) / (2 * h)
+        assert fd == pytest.approx((grad * d).sum(), rel=2e-7, abs=1e-9)
+
+
+def test_vjp_i_and_j_sides_separately():
+    # Distinct i and j sets: the i-side and j-side cotangents each match FD.
+    g = np.random.default_rng(3)
+    xi, vi = g.normal(0, 1, (3, 7)), g.normal(0, 1, (3, 7))
+    xj, vj, mj = g.normal(0, 1, (3, 11)), g.normal(0, 1, (3, 11)), g.uniform(0.1, 1, 11)
+    ga, gj, gp = g.normal(size=(3, 7)), g.normal(size=(3, 7)), g.normal(size=7)
+    eps = 0.1
+    gxi, gvi, gxj, gvj, gmj = oracle.force_vjp(xi, vi, xj, vj, mj, eps, ga, gj, gp)
+    h = 1e-6
+
+    def L(xi_, vi_, xj_, vj_, mj_):
+        a, j, p = oracle.force(xi_, vi_, xj_, vj_, mj_, eps)
+        return (ga * a).sum() + (gj * j).sum() + (gp * p).sum()
+
+    args = [xi, vi, xj, vj, mj]
+    for k, grad in enumerate((gxi, gvi, gxj, gvj, gmj)):
+        d = g.normal(size=grad.shape)
+        up = [a.copy() for a in args]; dn = [a.copy() for a in args]
+        up[k] += h * d; dn[k] -= h * d
+        fd = (L(*up) - L(*dn)) / (2 * h)
+        assert fd == pytest.approx((grad * d).sum(), rel=2e-7, abs=1e-9)
+
+
+def test_vjp_translation_and_galilean_invariance():
+    n = 40
+    x, v, m = system(n, 4)
+    g = np.random.default_rng(5)
+    ga, gj, gp = g.normal(size=(3, n)), g.normal(size=(3, n)), g.normal(size=n)
+    gxi, gvi, gxj, gvj, _ = oracle.force_vjp(x, v, x, v, m, 0.02, ga, gj, gp,
+                                             iself=np.arange(n))
+    sx = (gxi + gxj).sum(axis=1); sv = (gvi + gvj).sum(axis=1)
+    scale = np.abs(gxi).sum()
+    assert np.all(np.abs(sx) < 1e-12 * scale)
+    assert np.all(np.abs(sv) < 1e-12 * np.abs(gvi).sum())
+
+
+def test_vjp_euler_homogeneity():
+    # Outputs are linear in the masses: sum_k m_k dL/dm_k = L.
+    # With eps = 0 they are homogeneous in (x, v) -> (l x, l v) of degree -2
+    # (a, jerk) and -1 (phi); in v alone, jerk has degree 1 and a, phi 0.
+    n = 30
+    x, v, m = system(n, 6)
+    g = np.random.default_rng(7)
+    ga, gj, gp = g.normal(size=(3, n)), g.normal(size=(3, n)), g.normal(size=n)
+    iself = np.arange(n)
+    a, j, p = oracle.force(x, v, x, v, m, 0.0, iself=iself)
+    La, Lj, Lp = (ga * a).sum(), (gj * j).sum(), (gp * p).sum()
+    gxi, gvi, gxj, gvj, gmj = oracle.force_vjp(x, v, x, v, m, 0.0, ga, gj, gp, iself=iself)
+    assert (m * gmj).sum() == pytest.approx(La + Lj + Lp, rel=1e-12)
+    gx, gv = gxi + gxj, gvi + gvj
+    assert (x * gx).sum() + (v * gv).sum() == pytest.approx(-2 * La - 2 * Lj - Lp, rel=1e-11)
+    assert (v * gv).sum() == pytest.approx(Lj, rel=1e-11)
+
+
+def test_vjp_null_cotangents_equal_zero_cotangents():
+    n = 12
+    x, v, m = system(n, 8)
+    ga = np.random.default_rng(9).normal(size=(3, n))
+    r1 = oracle.force_vjp(x, v, x, v, m, 0.1, ga, None, None, iself=np.arange(n))
+    r2 = oracle.force_vjp(x, v, x, v, m, 0.1, ga, np.zeros((3, n)), np.zeros(n),
+                          iself=np.arange(n))
+    for a, b in zip(r1, r2):
+        np.testing.assert_array_equal(a, b)
