@@ -1,0 +1,202 @@
+#!/usr/bin/env python3
+"""Throughput benchmark: one Hermite step of a 2^20-body Plummer sphere with
+every particle active, on one MI355X.
+
+A step is one pass of the whole hot path: active-block selection on integer
+ticks, float64 prediction of all particles and packing to the device
+layout, the O(N^2) pairwise acceleration/jerk/potential kernel, and the
+float64 corrector.  Inputs are resident in HBM before the timed region.
+
+Prints ONE JSON line (rank 0, N = 1):
+  value     whole-job interactions per second (Ginteractions/s), N^2 per step
+  roofline  the pairwise kernel against the FP32 vector peak, from HIP events
+            recorded around each kernel launch on its stream
+  cpu_baseline  the float64 oracle on a bounded i-subset on the host's cores
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+FLOPS_PER_INTERACTION = 60          # acc + jerk + potential convention (Eq. 3, k = 60)
+FP32_PEAK_TFLOPS = 157.3            # MI355X FP32 vector peak (256 CU x 64 x 2 x 2 x 2.4 GHz)
+PAPER_GINT_S = 1.0995116e12 / 279.4067 / 1e9   # 8800GTX, N = 2^20, Table 4 (context)
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "force_ds_plummer1m_traffic.txt")
+FORCE_SRC = os.path.join(ROOT, "paper_0707_0438_amd", "csrc", "force.hip")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def traffic_per_launch(prec: str):
+    """HBM bytes per launch of the pairwise kernel from the committed rocprofv3
+    counter summary, or None when it is missing or the kernel source changed
+    since the counters were taken."""
+    if prec != "ds" or not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    for ln in open(TRAFFIC_FILE):
+        if ":" in ln:
+            k, v = ln.split(":", 1)
+            kv[k.strip()] = v.strip()
+    sha = hashlib.sha256(open(FORCE_SRC, "rb").read()).hexdigest()
+    if kv.get("kernel_source_sha256") != sha:
+        return None
+    try:
+        return float(kv["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def time_steps(ctx, h, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        h.step()
+    torch.cuda.synchronize()
+    ctx.kernel_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    total_active = 0
+    for _ in range(steps):
+        na, _ = h.step()
+        total_active += na
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kms, launches = ctx.kernel_time()
+    ctx.kernel_timing(False)
+    return t1 - t0, total_active, kms, launches
+
+
+def cpu_baseline(p, eps, budget_s):
+    import numpy as np
+    import oracle
+    n = p.n
+    t0 = time.perf_counter()
+    oracle.force(p.pos[:, :16], p.vel[:, :16], p.pos, p.vel, p.mass, eps, iself=np.arange(16))
+    t16 = time.perf_counter() - t0
+    k = int(max(16, min(4096, budget_s / max(t16, 1e-6) * 16)))
+    sel = np.arange(k)
+    t0 = time.perf_counter()
+    oracle.force(p.pos[:, sel], p.vel[:, sel], p.pos, p.vel, p.mass, eps, iself=sel)
+    dt = time.perf_counter() - t0
+    return {"value": round(k * n / dt / 1e9, 6), "unit": "Ginteractions/s",
+            "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"float64 oracle force (acc+jerk+pot) of the first {k} particles against "
+                      f"all {n} (eps={eps}), {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=1 << 20)
+    ap.add_argument("--prec", choices=["ds", "fp32"], default="ds")
+    ap.add_argument("--compare-steps", type=int, default=3,
+                    help="steps timed in the other precision for comparison (0: skip)")
+    ap.add_argument("--cpu-budget", type=float, default=12.0,
+                    help="seconds of oracle work for the CPU baseline (0: skip)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
+              "(the multi-GPU sharding is described in the design notes, not built)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import nbody_inputs as ics
+    import paper_0707_0438_amd as nb
+
+    eps = 1e-4
+    n = args.n
+    log(f"[bench] generating Plummer N={n}")
+    p = ics.plummer(n, ics.seed_for(2))
+    X = torch.from_numpy(p.pos).to("cuda")
+    V = torch.from_numpy(p.vel).to("cuda")
+    M = torch.from_numpy(p.mass).to("cuda")
+    ctx = nb.Context(0)
+    results = {}
+    for prec, steps in ((args.prec, args.steps),
+                        ("fp32" if args.prec == "ds" else "ds", args.compare_steps)):
+        if steps <= 0:
+            continue
+        h = ctx.hermite(n, eps=eps, shared_dt_log2=-10, prec=prec)
+        log(f"[bench] {prec}: initial evaluation")
+        h.set_state(X, V, M)
+        torch.cuda.synchronize()
+        log(f"[bench] {prec}: {args.warmup} warm-up + {steps} timed steps")
+        wall, active, kms, launches = time_steps(ctx, h, steps, args.warmup)
+        inter = float(active) * n
+        results[prec] = {"wall": wall, "inter": inter, "kms": kms, "launches": launches,
+                         "tile": ctx.get_tile(n, n, prec), "steps": steps}
+        log(f"[bench] {prec}: {wall:.3f} s, {inter / wall / 1e9:.1f} Gint/s, "
+            f"kernel {kms / max(launches, 1):.2f} ms/launch")
+        h.close()
+    r = results[args.prec]
+    value = r["inter"] / r["wall"] / 1e9
+    k_ms = r["kms"] / max(r["launches"], 1)
+    achieved = FLOPS_PER_INTERACTION * float(n) * n / (k_ms * 1e-3) / 1e12
+    traffic = traffic_per_launch(args.prec)
+    line = {
+        "metric": "Ginteractions/s (acc+jerk) at N=2^20, % FP32 peak; adjoint/forward time",
+        "value": round(value, 3),
+        "unit": "Ginteractions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(r["wall"] / args.steps * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": round(value / PAPER_GINT_S, 2),
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "plummer1m_force: equal-mass Plummer sphere N=2^20 (seeded AHW sampling), "
+                        "eps=1e-4, all particles active; one step = block select + f64 predict/pack "
+                        "+ pairwise acc/jerk/pot + f64 Hermite corrector (shared dt 2^-10)",
+            "n": n, "eps": eps, "G": 1.0,
+            "prec": "ds_comp" if args.prec == "ds" else "fp32",
+            "tile": r["tile"],
+        },
+        "pct_fp32_peak": round(100.0 * FLOPS_PER_INTERACTION * value * 1e9 / (FP32_PEAK_TFLOPS * 1e12), 2),
+        "roofline": {
+            "bound": "alu",
+            "achieved": round(achieved, 3),
+            "peak": FP32_PEAK_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": round(achieved / FP32_PEAK_TFLOPS, 4),
+            "traffic": traffic,
+            "kernel": "force_kernel (pairwise acc+jerk+pot)",
+            "kernel_ms": round(k_ms, 3),
+            "launches": r["launches"],
+        },
+    }
+    other = "fp32" if args.prec == "ds" else "ds"
+    if other in results:
+        o = results[other]
+        ov = o["inter"] / o["wall"] / 1e9
+        line[f"{other}_compare"] = {
+            "value": round(ov, 3),
+            "ms_per_step": round(o["wall"] / o["steps"] * 1e3, 3),
+            "kernel_ms": round(o["kms"] / max(o["launches"], 1), 3),
+            "pct_fp32_peak": round(100.0 * FLOPS_PER_INTERACTION * ov * 1e9 / (FP32_PEAK_TFLOPS * 1e12), 2),
+        }
+    if args.cpu_budget > 0:
+        log("[bench] cpu baseline (oracle)")
+        line["cpu_baseline"] = cpu_baseline(p, eps, args.cpu_budget)
+    ctx.close()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -113,12 +113,32 @@ const char *nbody_last_error(const nbody_ctx *ctx);
 /* NBODY_ABI_VERSION of the loaded library. */
 int nbody_abi_version(void);
 
+/* Kernel timing.  While enabled, every launch of the pairwise kernel made
+ * through this context is bracketed by two HIP events recorded on the
+ * launch stream.  nbody_kernel_time waits for the recorded events, returns
+ * the summed kernel time in milliseconds and the number of launches (HOST
+ * outputs) and starts a new tally.  The events stay owned by the context. */
+int nbody_kernel_timing(nbody_ctx *ctx, int enable);
+int nbody_kernel_time(nbody_ctx *ctx, double *total_ms, int64_t *launches);
+
 /* Force the launch shape used for `prec` (all fields > 0 except split,
  * which may be 0), or clear the override when t is NULL. */
 int nbody_set_tile(nbody_ctx *ctx, nbody_prec prec, const nbody_tile *t);
 
 /* The launch shape the next nbody_force call would use for this shape. */
 int nbody_get_tile(nbody_ctx *ctx, nbody_prec prec, int64_t n_i, int64_t n_j, nbody_tile *t);
+
+/* Autotuner (the number of threads per bundle is the tuning knob the paper
+ * leaves to the user, Section 5): time every launch shape tile_j x ipt x wg
+ * (split chosen from the shape) on the given inputs, `reps` timed
+ * evaluations each after one warm-up, keep the fastest for this precision
+ * and shape bucket (floor log2 of n_i and n_j), and write the cache file if
+ * the context has one.  `out` receives the last evaluation.  *best and
+ * *best_ms (HOST, may be NULL) report the choice and its time per
+ * evaluation in milliseconds.  Synchronises `stream`. */
+int nbody_autotune(nbody_ctx *ctx, hipStream_t stream, nbody_prec prec, double G, double eps,
+                   int64_t n_i, nbody_src I, int64_t n_j, nbody_src J, nbody_out out, int reps,
+                   nbody_tile *best, double *best_ms);
 
 /* ---- force (Eq. 1, Section 3) -------------------------------------------- */
 
@@ -208,6 +228,15 @@ int nbody_hermite_energy(nbody_hermite *h, hipStream_t stream, double *ekin, dou
 int64_t nbody_hermite_state_bytes(const nbody_hermite *h);
 int nbody_hermite_save(nbody_hermite *h, hipStream_t stream, void *host_buf);
 int nbody_hermite_load(nbody_hermite *h, hipStream_t stream, const void *host_buf);
+
+/* The power-of-two step rule applied by the corrector (Section 3.1 block
+ * steps), evaluated on the host: largest 2^k <= crit (time units), clamped
+ * to [2^lmin, 2^lmax]; a criterion that is zero, negative or not finite
+ * gives 2^lmin; dt_old <= 0 is a first step; a smaller level is taken at
+ * once, a larger one only as one doubling when t_new is a multiple of
+ * 2 dt_old.  Ticks in and out; -1 for an invalid level range.  No device
+ * work. */
+int64_t nbody_block_level(double crit, int64_t dt_old, int64_t t_new, int lmin, int lmax);
 
 #ifdef __cplusplus
 }

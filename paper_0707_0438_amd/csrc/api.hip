@@ -1,0 +1,862 @@
+// Host side of the C ABI declared in include/nbody.h: argument checks,
+// context-owned scratch memory, launch-shape choice and the Hermite
+// block-step driver.  All particle arithmetic runs in the kernels of
+// force.hip and hermite.hip.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "nbody.h"
+#include "nbody_internal.h"
+#include "tune.h"
+
+using namespace nb;
+
+namespace {
+
+constexpr int64_t kMaxN = 2147483647LL;
+
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+};
+
+}  // namespace
+
+struct nbody_ctx {
+    int device = -1;          // -1: argument-checking context without a device
+    std::string err;
+    DevBuf ipack, jpack, part, sel, scratch64;
+    bool have_override[2] = {false, false};
+    nbody_tile override_tile[2];
+    nb::TuneCache tune;
+    int alloc_count = 0;
+    int fail_alloc_at = 0;    // debug: NBODY_DEBUG_FAIL_ALLOC=k fails the k-th allocation
+    // kernel timing: event pairs recorded around each pairwise-kernel launch
+    bool timing = false;
+    std::vector<hipEvent_t> ev;   // 2 per launch
+    size_t ev_used = 0;
+};
+
+struct nbody_hermite {
+    nbody_ctx* ctx = nullptr;
+    int64_t n = 0;
+    nbody_hermite_opts o{};
+    bool has_state = false;
+    // float64 state rows: x y z vx vy vz ax ay az jx jy jz m ; pot scratch
+    double* s[13] = {};
+    double* f[7] = {};        // block forces (a, jerk, pot) [n]
+    double* pred[6] = {};     // predicted x, v for energy
+    int64_t* t = nullptr;
+    int64_t* dt = nullptr;
+    int32_t* idx = nullptr;
+    int64_t* sel2 = nullptr;  // device [2]: n_act, t_next
+    int64_t* tnow = nullptr;  // device scalar: latest block time
+    double* e2 = nullptr;     // device [2]
+    int64_t t_ticks = 0;
+    int64_t steps = 0, sum_active = 0;
+    void* block = nullptr;    // single allocation holding everything above
+};
+
+static int set_err(nbody_ctx* c, int code, const char* fmt, ...) {
+    if (c) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        c->err = buf;
+    }
+    return code;
+}
+
+static int hip_err(nbody_ctx* c, hipError_t e, const char* what) {
+    return set_err(c, NBODY_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+// Switch to the context's device for the duration of a call.
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = false;
+    explicit DeviceGuard(int dev) {
+        if (dev < 0) return;
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        ok = hipSetDevice(dev) == hipSuccess;
+    }
+    ~DeviceGuard() {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+static int dev_alloc(nbody_ctx* c, DevBuf& b, size_t bytes) {
+    if (b.bytes >= bytes) return NBODY_OK;
+    ++c->alloc_count;
+    if (c->fail_alloc_at > 0 && c->alloc_count == c->fail_alloc_at)
+        return set_err(c, NBODY_ERR_NOMEM, "device allocation of %zu bytes failed (injected)", bytes);
+    if (b.p) {
+        (void)hipFree(b.p);
+        b.p = nullptr;
+        b.bytes = 0;
+    }
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return set_err(c, NBODY_ERR_NOMEM, "hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
+    }
+    b.p = p;
+    b.bytes = bytes;
+    return NBODY_OK;
+}
+
+static bool aligned8(const void* p) { return ((uintptr_t)p & 7u) == 0; }
+
+static int check_src(nbody_ctx* c, const nbody_src& s, bool need_m, const char* name) {
+    const double* rows[7] = {s.x, s.y, s.z, s.vx, s.vy, s.vz, s.m};
+    for (int k = 0; k < 7; ++k) {
+        if (k == 6 && !need_m) continue;
+        if (!rows[k]) return set_err(c, NBODY_ERR_ARG, "%s: row %d is NULL", name, k);
+        if (!aligned8(rows[k])) return set_err(c, NBODY_ERR_ARG, "%s: row %d is not 8-byte aligned", name, k);
+    }
+    return NBODY_OK;
+}
+
+static int check_out(nbody_ctx* c, const nbody_out& o) {
+    double* rows[7] = {o.ax, o.ay, o.az, o.jx, o.jy, o.jz, o.pot};
+    for (int k = 0; k < 7; ++k) {
+        if (!rows[k]) return set_err(c, NBODY_ERR_ARG, "out: row %d is NULL", k);
+        if (!aligned8(rows[k])) return set_err(c, NBODY_ERR_ARG, "out: row %d is not 8-byte aligned", k);
+    }
+    return NBODY_OK;
+}
+
+static bool valid_tile(const nbody_tile& t) {
+    const bool tj = t.tile_j == 64 || t.tile_j == 128 || t.tile_j == 256;
+    const bool ip = t.ipt == 1 || t.ipt == 2 || t.ipt == 4;
+    const bool wg = t.wg == 128 || t.wg == 256;
+    return tj && ip && wg && t.split >= 0 && t.split <= 4096;
+}
+
+// Number of j-ranges for an i-list of ni against nj: enough work-groups to
+// cover the 256 CUs several times, but at least two tiles per range.
+static int choose_split(int64_t ni, int64_t nj, const nbody_tile& t) {
+    const int64_t per_blk = (int64_t)t.wg * t.ipt;
+    const int64_t nblk = (ni + per_blk - 1) / per_blk;
+    const int64_t target = 2048;
+    if (nblk <= 0 || nblk >= target / 2) return 1;
+    int64_t S = (target + nblk - 1) / nblk;
+    const int64_t smax = std::max<int64_t>(1, nj / (2 * (int64_t)t.tile_j));
+    S = std::min(S, smax);
+    return (int)std::max<int64_t>(1, S);
+}
+
+static nbody_tile default_tile(int prec, int64_t ni) {
+    nbody_tile t;
+    t.tile_j = 128;
+    t.wg = 256;
+    t.ipt = ni >= 65536 ? 2 : 1;
+    t.split = 0;
+    (void)prec;
+    return t;
+}
+
+static nbody_tile pick_tile(nbody_ctx* c, int prec, int64_t ni, int64_t nj) {
+    nbody_tile t;
+    if (c->have_override[prec]) {
+        t = c->override_tile[prec];
+    } else if (!c->tune.lookup(prec, ni, nj, &t)) {
+        t = default_tile(prec, ni);
+    }
+    if (t.split <= 0) t.split = choose_split(ni, nj, t);
+    return t;
+}
+
+// Core evaluation: i records (ipack, iidx) against j records (jpack).
+static int run_force(nbody_ctx* c, hipStream_t st, int prec, double G, double eps, int64_t ni,
+                     const float4* ipack, const int32_t* iidx, const int32_t* iself, int self_mode,
+                     int64_t nj, const float4* jpack, double* const out[7], const nbody_tile* forced) {
+    if (ni == 0) return NBODY_OK;
+    nbody_tile t = forced ? *forced : pick_tile(c, prec, ni, nj);
+    if (t.split <= 0) t.split = choose_split(ni, nj, t);
+    const bool eps0 = eps == 0.0;
+    int ipt = t.ipt, tj = t.tile_j, wg = t.wg;
+    if (eps0 && !force_variant_exists(prec, ipt, tj, wg, true)) {
+        ipt = ipt >= 2 ? 2 : 1;
+        tj = 128;
+        wg = 256;
+    }
+    const int64_t per_blk = (int64_t)wg * ipt;
+    const int nb = (int)((ni + per_blk - 1) / per_blk);
+    int64_t jchunk = (nj + t.split - 1) / t.split;
+    jchunk = ((jchunk + tj - 1) / tj) * tj;
+    if (jchunk <= 0) jchunk = tj;
+    const int S = (int)std::max<int64_t>(1, (nj + jchunk - 1) / jchunk);
+
+    ForceArgs a{};
+    a.ipack = ipack;
+    a.iidx = iidx;
+    a.ni = (int)ni;
+    a.jpack = jpack;
+    a.nj = (int)nj;
+    a.jchunk = (int)jchunk;
+    a.eps2 = (float)(eps * eps);
+    a.G = G;
+    a.iself = iself;
+    a.self_mode = self_mode;
+    for (int q = 0; q < 7; ++q) a.out[q] = out[q];
+    a.partial = S > 1 ? 1 : 0;
+    if (S > 1) {
+        int rc = dev_alloc(c, c->part, sizeof(float2) * 7 * (size_t)S * (size_t)ni);
+        if (rc) return rc;
+        a.part = (float2*)c->part.p;
+    }
+    hipEvent_t tb = nullptr, te = nullptr;
+    if (c->timing) {
+        while (c->ev.size() < c->ev_used + 2) {
+            hipEvent_t x;
+            if (hipEventCreate(&x) != hipSuccess) return set_err(c, NBODY_ERR_DEVICE, "event create");
+            c->ev.push_back(x);
+        }
+        tb = c->ev[c->ev_used];
+        te = c->ev[c->ev_used + 1];
+        c->ev_used += 2;
+        if (hipEventRecord(tb, st) != hipSuccess) return set_err(c, NBODY_ERR_DEVICE, "event record");
+    }
+    hipError_t e = launch_force(prec, ipt, tj, wg, eps0, nb, S, a, st);
+    if (e != hipSuccess) return hip_err(c, e, "force kernel launch");
+    if (te && hipEventRecord(te, st) != hipSuccess) return set_err(c, NBODY_ERR_DEVICE, "event record");
+    if (S > 1) {
+        ReduceArgs r{};
+        r.ni = (int)ni;
+        r.nj = (int)nj;
+        r.S = S;
+        r.prec = prec;
+        r.eps0 = eps0 ? 1 : 0;
+        r.part = a.part;
+        r.jpack = jpack;
+        r.iidx = iidx;
+        r.iself = iself;
+        r.self_mode = self_mode;
+        r.eps2 = a.eps2;
+        r.G = G;
+        for (int q = 0; q < 7; ++q) r.out[q] = out[q];
+        e = launch_reduce(r, st);
+        if (e != hipSuccess) return hip_err(c, e, "split reduce launch");
+    }
+    return NBODY_OK;
+}
+
+static int pack_rows(nbody_ctx* c, hipStream_t st, int prec, int64_t n, const nbody_src& s,
+                     bool with_m, DevBuf& dst) {
+    const size_t bytes = sizeof(float4) * (size_t)rec_words(prec) * (size_t)std::max<int64_t>(n, 1);
+    int rc = dev_alloc(c, dst, bytes);
+    if (rc) return rc;
+    PackArgs p{};
+    p.n = (int)n;
+    p.prec = prec;
+    p.x = s.x; p.y = s.y; p.z = s.z;
+    p.vx = s.vx; p.vy = s.vy; p.vz = s.vz;
+    p.m = with_m ? s.m : nullptr;
+    p.out = (float4*)dst.p;
+    hipError_t e = launch_pack(p, st);
+    if (e != hipSuccess) return hip_err(c, e, "pack launch");
+    return NBODY_OK;
+}
+
+static bool same_src(const nbody_src& a, const nbody_src& b) {
+    return a.x == b.x && a.y == b.y && a.z == b.z && a.vx == b.vx && a.vy == b.vy && a.vz == b.vz;
+}
+
+extern "C" {
+
+int nbody_abi_version(void) { return NBODY_ABI_VERSION; }
+
+int nbody_create(nbody_ctx** ctx, int device, const char* tune_cache_path) {
+    if (!ctx) return NBODY_ERR_ARG;
+    *ctx = nullptr;
+    if (device < -1) return NBODY_ERR_ARG;
+    nbody_ctx* c = new (std::nothrow) nbody_ctx();
+    if (!c) return NBODY_ERR_NOMEM;
+    if (const char* f = getenv("NBODY_DEBUG_FAIL_ALLOC")) c->fail_alloc_at = atoi(f);
+    const char* path = tune_cache_path ? tune_cache_path : getenv("NBODY_TUNE_CACHE");
+    if (path && *path) c->tune.set_path(path);
+    if (device >= 0) {
+        int count = 0;
+        hipError_t e = hipGetDeviceCount(&count);
+        if (e != hipSuccess || device >= count) {
+            (void)hipGetLastError();
+            delete c;
+            return NBODY_ERR_DEVICE;
+        }
+        hipDeviceProp_t prop;
+        e = hipGetDeviceProperties(&prop, device);
+        if (e != hipSuccess) {
+            delete c;
+            return NBODY_ERR_DEVICE;
+        }
+        c->tune.set_arch(prop.gcnArchName);
+        c->tune.load();
+    }
+    c->device = device;
+    *ctx = c;
+    return NBODY_OK;
+}
+
+int nbody_destroy(nbody_ctx* c) {
+    if (!c) return NBODY_OK;
+    if (c->device >= 0) {
+        DeviceGuard g(c->device);
+        for (hipEvent_t x : c->ev) (void)hipEventDestroy(x);
+        DevBuf* bufs[] = {&c->ipack, &c->jpack, &c->part, &c->sel, &c->scratch64};
+        for (DevBuf* b : bufs)
+            if (b->p) (void)hipFree(b->p);
+    }
+    delete c;
+    return NBODY_OK;
+}
+
+const char* nbody_last_error(const nbody_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+static int need_device(nbody_ctx* c) {
+    if (c->device < 0)
+        return set_err(c, NBODY_ERR_UNSUPPORTED, "context has no device (created with device -1)");
+    return NBODY_OK;
+}
+
+int nbody_reserve(nbody_ctx* c, int64_t max_i, int64_t max_j) {
+    if (!c) return NBODY_ERR_ARG;
+    if (max_i < 0 || max_j < 0 || max_i > kMaxN || max_j > kMaxN)
+        return set_err(c, NBODY_ERR_ARG, "reserve: sizes must be in [0, 2^31-1]");
+    if (int rc = need_device(c)) return rc;
+    DeviceGuard g(c->device);
+    const size_t ni = (size_t)std::max<int64_t>(max_i, 1), nj = (size_t)std::max<int64_t>(max_j, 1);
+    int rc = dev_alloc(c, c->ipack, sizeof(float4) * kRecDS * ni);
+    if (!rc) rc = dev_alloc(c, c->jpack, sizeof(float4) * kRecDS * nj);
+    return rc;
+}
+
+int nbody_sync(nbody_ctx* c, hipStream_t st) {
+    if (!c) return NBODY_ERR_ARG;
+    if (int rc = need_device(c)) return rc;
+    DeviceGuard g(c->device);
+    hipError_t e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_err(c, e, "stream synchronize");
+    return NBODY_OK;
+}
+
+int nbody_kernel_timing(nbody_ctx* c, int enable) {
+    if (!c) return NBODY_ERR_ARG;
+    if (enable != 0 && enable != 1) return set_err(c, NBODY_ERR_ARG, "enable must be 0 or 1");
+    if (int rc = need_device(c)) return rc;
+    c->timing = enable == 1;
+    c->ev_used = 0;
+    return NBODY_OK;
+}
+
+int nbody_kernel_time(nbody_ctx* c, double* total_ms, int64_t* launches) {
+    if (!c) return NBODY_ERR_ARG;
+    if (!total_ms || !launches) return set_err(c, NBODY_ERR_ARG, "NULL output");
+    if (int rc = need_device(c)) return rc;
+    DeviceGuard g(c->device);
+    double tot = 0.0;
+    for (size_t k = 0; k + 1 < c->ev_used; k += 2) {
+        hipError_t e = hipEventSynchronize(c->ev[k + 1]);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, c->ev[k], c->ev[k + 1]);
+        if (e != hipSuccess) return hip_err(c, e, "kernel timing");
+        tot += ms;
+    }
+    *total_ms = tot;
+    *launches = (int64_t)(c->ev_used / 2);
+    c->ev_used = 0;
+    return NBODY_OK;
+}
+
+int nbody_set_tile(nbody_ctx* c, nbody_prec prec, const nbody_tile* t) {
+    if (!c) return NBODY_ERR_ARG;
+    if (prec != NBODY_PREC_FP32 && prec != NBODY_PREC_DS_COMP)
+        return set_err(c, NBODY_ERR_ARG, "unknown precision %d", (int)prec);
+    if (!t) {
+        c->have_override[prec] = false;
+        return NBODY_OK;
+    }
+    if (!valid_tile(*t))
+        return set_err(c, NBODY_ERR_ARG, "tile (tile_j=%d ipt=%d wg=%d split=%d) not supported", t->tile_j,
+                       t->ipt, t->wg, t->split);
+    c->override_tile[prec] = *t;
+    c->have_override[prec] = true;
+    return NBODY_OK;
+}
+
+int nbody_get_tile(nbody_ctx* c, nbody_prec prec, int64_t ni, int64_t nj, nbody_tile* t) {
+    if (!c || !t) return NBODY_ERR_ARG;
+    if (prec != NBODY_PREC_FP32 && prec != NBODY_PREC_DS_COMP)
+        return set_err(c, NBODY_ERR_ARG, "unknown precision %d", (int)prec);
+    if (ni < 0 || nj < 0 || ni > kMaxN || nj > kMaxN) return set_err(c, NBODY_ERR_ARG, "bad sizes");
+    *t = pick_tile(c, prec, ni, nj);
+    return NBODY_OK;
+}
+
+static int check_common(nbody_ctx* c, nbody_prec prec, double G, double eps) {
+    if (prec != NBODY_PREC_FP32 && prec != NBODY_PREC_DS_COMP)
+        return set_err(c, NBODY_ERR_ARG, "unknown precision %d", (int)prec);
+    if (!isfinite(G)) return set_err(c, NBODY_ERR_ARG, "G must be finite");
+    if (!isfinite(eps) || eps < 0.0) return set_err(c, NBODY_ERR_ARG, "eps must be finite and >= 0");
+    return NBODY_OK;
+}
+
+int nbody_force(nbody_ctx* c, hipStream_t st, nbody_prec prec, double G, double eps, int64_t n_i,
+                nbody_src I, const int32_t* i_self, int64_t n_j, nbody_src J, nbody_out out) {
+    if (!c) return NBODY_ERR_ARG;
+    if (int rc = check_common(c, prec, G, eps)) return rc;
+    if (n_i < 0 || n_j < 0) return set_err(c, NBODY_ERR_ARG, "n_i and n_j must be >= 0");
+    if (n_i > kMaxN || n_j > kMaxN) return set_err(c, NBODY_ERR_ARG, "n_i and n_j must be <= 2^31-1");
+    if (n_i > 0) {
+        if (int rc = check_src(c, I, false, "I")) return rc;
+        if (int rc = check_out(c, out)) return rc;
+    }
+    if (n_j > 0)
+        if (int rc = check_src(c, J, true, "J")) return rc;
+    if (n_i > 0 && n_j == 0 && i_self)
+        return set_err(c, NBODY_ERR_ARG, "i_self given with an empty j set");
+    if (int rc = need_device(c)) return rc;
+    if (n_i == 0) return NBODY_OK;
+    DeviceGuard g(c->device);
+    if (!g.ok) return set_err(c, NBODY_ERR_DEVICE, "hipSetDevice(%d) failed", c->device);
+    const int p = (int)prec;
+    int rc = pack_rows(c, st, p, n_j, J, true, c->jpack);
+    if (rc) return rc;
+    const float4* ip = (const float4*)c->jpack.p;
+    if (!(n_i == n_j && same_src(I, J))) {
+        rc = pack_rows(c, st, p, n_i, I, false, c->ipack);
+        if (rc) return rc;
+        ip = (const float4*)c->ipack.p;
+    }
+    double* o[7] = {out.ax, out.ay, out.az, out.jx, out.jy, out.jz, out.pot};
+    return run_force(c, st, p, G, eps, n_i, ip, nullptr, i_self, 0, n_j, (const float4*)c->jpack.p, o,
+                     nullptr);
+}
+
+int nbody_select_active(nbody_ctx* c, hipStream_t st, int64_t n, const int64_t* t, const int64_t* dt,
+                        int32_t* idx, int64_t* n_act, int64_t* t_next) {
+    if (!c) return NBODY_ERR_ARG;
+    if (n < 0 || n > kMaxN) return set_err(c, NBODY_ERR_ARG, "n must be in [0, 2^31-1]");
+    if (!n_act || !t_next) return set_err(c, NBODY_ERR_ARG, "n_act and t_next must be host pointers");
+    if (n > 0 && (!t || !dt || !idx)) return set_err(c, NBODY_ERR_ARG, "t, dt and idx must not be NULL");
+    if (int rc = need_device(c)) return rc;
+    if (n == 0) {
+        *n_act = 0;
+        *t_next = 0;
+        return NBODY_OK;
+    }
+    DeviceGuard g(c->device);
+    int rc = dev_alloc(c, c->sel, 2 * sizeof(int64_t));
+    if (rc) return rc;
+    hipError_t e = launch_select((int)n, t, dt, idx, (int64_t*)c->sel.p, st);
+    if (e != hipSuccess) return hip_err(c, e, "select launch");
+    int64_t h[2];
+    e = hipMemcpyAsync(h, c->sel.p, sizeof h, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_err(c, e, "select readback");
+    *n_act = h[0];
+    *t_next = h[1];
+    return NBODY_OK;
+}
+
+// ---- Hermite driver ---------------------------------------------------------
+
+int nbody_hermite_create(nbody_ctx* c, nbody_hermite** hp, int64_t n, const nbody_hermite_opts* o) {
+    if (!c) return NBODY_ERR_ARG;
+    if (!hp || !o) return set_err(c, NBODY_ERR_ARG, "NULL argument");
+    *hp = nullptr;
+    if (n <= 0 || n > kMaxN) return set_err(c, NBODY_ERR_ARG, "n must be in [1, 2^31-1]");
+    if (int rc = check_common(c, o->prec, o->G, o->eps)) return rc;
+    if (!(o->eta > 0.0) || !isfinite(o->eta) || !(o->eta_start > 0.0) || !isfinite(o->eta_start))
+        return set_err(c, NBODY_ERR_ARG, "eta and eta_start must be positive and finite");
+    if (o->shared_dt_log2 != 0) {
+        if (o->shared_dt_log2 < -20 || o->shared_dt_log2 > -1)
+            return set_err(c, NBODY_ERR_ARG, "shared_dt_log2 must be in [-20, -1] (or 0 for block steps)");
+    } else if (o->dt_min_log2 < -20 || o->dt_max_log2 > 0 || o->dt_min_log2 > o->dt_max_log2) {
+        return set_err(c, NBODY_ERR_ARG, "need -20 <= dt_min_log2 <= dt_max_log2 <= 0");
+    }
+    if (int rc = need_device(c)) return rc;
+    DeviceGuard g(c->device);
+    nbody_hermite* h = new (std::nothrow) nbody_hermite();
+    if (!h) return set_err(c, NBODY_ERR_NOMEM, "host allocation failed");
+    h->ctx = c;
+    h->n = n;
+    h->o = *o;
+    const size_t nn = (size_t)n;
+    const size_t bytes = sizeof(double) * nn * (13 + 1 + 7 + 6) + sizeof(int64_t) * nn * 2 +
+                         sizeof(int32_t) * nn + sizeof(int64_t) * 8 + sizeof(double) * 2 + 4096;
+    ++c->alloc_count;
+    if (c->fail_alloc_at > 0 && c->alloc_count == c->fail_alloc_at) {
+        delete h;
+        return set_err(c, NBODY_ERR_NOMEM, "device allocation of %zu bytes failed (injected)", bytes);
+    }
+    hipError_t e = hipMalloc(&h->block, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        delete h;
+        return set_err(c, NBODY_ERR_NOMEM, "hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
+    }
+    char* p = (char*)h->block;
+    auto take = [&](size_t b) {
+        char* r = p;
+        p += (b + 255) & ~(size_t)255;
+        return (void*)r;
+    };
+    for (int k = 0; k < 13; ++k) h->s[k] = (double*)take(sizeof(double) * nn);
+    for (int k = 0; k < 7; ++k) h->f[k] = (double*)take(sizeof(double) * nn);
+    for (int k = 0; k < 6; ++k) h->pred[k] = (double*)take(sizeof(double) * nn);
+    h->t = (int64_t*)take(sizeof(int64_t) * nn);
+    h->dt = (int64_t*)take(sizeof(int64_t) * nn);
+    h->idx = (int32_t*)take(sizeof(int32_t) * nn);
+    h->sel2 = (int64_t*)take(sizeof(int64_t) * 2);
+    h->tnow = (int64_t*)take(sizeof(int64_t));
+    h->e2 = (double*)take(sizeof(double) * 2);
+    *hp = h;
+    return NBODY_OK;
+}
+
+int nbody_hermite_destroy(nbody_hermite* h) {
+    if (!h) return NBODY_OK;
+    if (h->block) {
+        DeviceGuard g(h->ctx->device);
+        (void)hipFree(h->block);
+    }
+    delete h;
+    return NBODY_OK;
+}
+
+static nbody_src state_src(nbody_hermite* h) {
+    nbody_src s;
+    s.x = h->s[0]; s.y = h->s[1]; s.z = h->s[2];
+    s.vx = h->s[3]; s.vy = h->s[4]; s.vz = h->s[5];
+    s.m = h->s[12];
+    return s;
+}
+
+int nbody_hermite_set_state(nbody_hermite* h, hipStream_t st, nbody_src P) {
+    if (!h) return NBODY_ERR_ARG;
+    nbody_ctx* c = h->ctx;
+    if (int rc = check_src(c, P, true, "P")) return rc;
+    DeviceGuard g(c->device);
+    const size_t b = sizeof(double) * (size_t)h->n;
+    const double* src[7] = {P.x, P.y, P.z, P.vx, P.vy, P.vz, P.m};
+    const int dst[7] = {0, 1, 2, 3, 4, 5, 12};
+    for (int k = 0; k < 7; ++k) {
+        hipError_t e = hipMemcpyAsync(h->s[dst[k]], src[k], b, hipMemcpyDeviceToDevice, st);
+        if (e != hipSuccess) return hip_err(c, e, "state copy");
+    }
+    hipError_t e = launch_fill_i64(h->t, (int)h->n, 0, st);
+    if (e == hipSuccess) e = launch_fill_i64(h->tnow, 1, 0, st);
+    if (e != hipSuccess) return hip_err(c, e, "state clear");
+    // initial a, jerk of every particle (self excluded), then first steps
+    const int p = (int)h->o.prec;
+    int rc = pack_rows(c, st, p, h->n, state_src(h), true, c->jpack);
+    if (rc) return rc;
+    double* o[7] = {h->s[6], h->s[7], h->s[8], h->s[9], h->s[10], h->s[11], h->f[6]};
+    rc = run_force(c, st, p, h->o.G, h->o.eps, h->n, (const float4*)c->jpack.p, nullptr, nullptr, 2,
+                   h->n, (const float4*)c->jpack.p, o, nullptr);
+    if (rc) return rc;
+    InitDtArgs a{};
+    a.n = (int)h->n;
+    a.ax = h->s[6]; a.ay = h->s[7]; a.az = h->s[8];
+    a.jx = h->s[9]; a.jy = h->s[10]; a.jz = h->s[11];
+    a.t = h->t;
+    a.dt = h->dt;
+    a.eta_s = h->o.eta_start;
+    a.lmin = h->o.dt_min_log2;
+    a.lmax = h->o.dt_max_log2;
+    a.shared_log2 = h->o.shared_dt_log2;
+    e = launch_init_dt(a, st);
+    if (e != hipSuccess) return hip_err(c, e, "init dt launch");
+    h->has_state = true;
+    h->t_ticks = 0;
+    h->steps = 0;
+    h->sum_active = 0;
+    return NBODY_OK;
+}
+
+static int hermite_step_impl(nbody_hermite* h, hipStream_t st, int64_t t_limit, int64_t* n_active,
+                             int64_t* t_ticks, bool* stopped) {
+    nbody_ctx* c = h->ctx;
+    const int n = (int)h->n;
+    hipError_t e = launch_select(n, h->t, h->dt, h->idx, h->sel2, st);
+    if (e != hipSuccess) return hip_err(c, e, "select launch");
+    int64_t hs[2];
+    e = hipMemcpyAsync(hs, h->sel2, sizeof hs, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_err(c, e, "block size readback");
+    const int64_t na = hs[0], tn = hs[1];
+    if (stopped) *stopped = false;
+    if (tn > t_limit || na <= 0) {
+        if (stopped) *stopped = true;
+        if (n_active) *n_active = 0;
+        if (t_ticks) *t_ticks = h->t_ticks;
+        return NBODY_OK;
+    }
+    const int p = (int)h->o.prec;
+    int rc = dev_alloc(c, c->jpack, sizeof(float4) * rec_words(p) * (size_t)n);
+    if (rc) return rc;
+    PackArgs pa{};
+    pa.n = n;
+    pa.prec = p;
+    pa.x = h->s[0]; pa.y = h->s[1]; pa.z = h->s[2];
+    pa.vx = h->s[3]; pa.vy = h->s[4]; pa.vz = h->s[5];
+    pa.m = h->s[12];
+    pa.ax = h->s[6]; pa.ay = h->s[7]; pa.az = h->s[8];
+    pa.jx = h->s[9]; pa.jy = h->s[10]; pa.jz = h->s[11];
+    pa.t = h->t;
+    pa.tnext = h->sel2 + 1;
+    pa.out = (float4*)c->jpack.p;
+    e = launch_pack(pa, st);
+    if (e != hipSuccess) return hip_err(c, e, "predict/pack launch");
+    rc = run_force(c, st, p, h->o.G, h->o.eps, na, (const float4*)c->jpack.p, h->idx, nullptr, 1, n,
+                   (const float4*)c->jpack.p, h->f, nullptr);
+    if (rc) return rc;
+    CorrectArgs ca{};
+    ca.n_act = (int)na;
+    ca.idx = h->idx;
+    ca.tnext = h->sel2 + 1;
+    ca.x = h->s[0]; ca.y = h->s[1]; ca.z = h->s[2];
+    ca.vx = h->s[3]; ca.vy = h->s[4]; ca.vz = h->s[5];
+    ca.ax = h->s[6]; ca.ay = h->s[7]; ca.az = h->s[8];
+    ca.jx = h->s[9]; ca.jy = h->s[10]; ca.jz = h->s[11];
+    ca.t = h->t;
+    ca.dt = h->dt;
+    for (int k = 0; k < 6; ++k) ca.f[k] = h->f[k];
+    ca.eta = h->o.eta;
+    ca.lmin = h->o.dt_min_log2;
+    ca.lmax = h->o.dt_max_log2;
+    ca.shared = h->o.shared_dt_log2 != 0;
+    e = launch_correct(ca, st);
+    if (e != hipSuccess) return hip_err(c, e, "corrector launch");
+    e = hipMemcpyAsync(h->tnow, h->sel2 + 1, sizeof(int64_t), hipMemcpyDeviceToDevice, st);
+    if (e != hipSuccess) return hip_err(c, e, "block time copy");
+    h->t_ticks = tn;
+    h->steps += 1;
+    h->sum_active += na;
+    if (n_active) *n_active = na;
+    if (t_ticks) *t_ticks = tn;
+    return NBODY_OK;
+}
+
+int nbody_hermite_step(nbody_hermite* h, hipStream_t st, int64_t* n_active, int64_t* t_ticks) {
+    if (!h) return NBODY_ERR_ARG;
+    if (!h->has_state) return set_err(h->ctx, NBODY_ERR_STATE, "hermite: set_state or load first");
+    DeviceGuard g(h->ctx->device);
+    return hermite_step_impl(h, st, INT64_MAX, n_active, t_ticks, nullptr);
+}
+
+int nbody_hermite_advance(nbody_hermite* h, hipStream_t st, int64_t t_end, nbody_hermite_stats* stats) {
+    if (!h) return NBODY_ERR_ARG;
+    if (!h->has_state) return set_err(h->ctx, NBODY_ERR_STATE, "hermite: set_state or load first");
+    DeviceGuard g(h->ctx->device);
+    for (;;) {
+        bool stopped = false;
+        int rc = hermite_step_impl(h, st, t_end, nullptr, nullptr, &stopped);
+        if (rc) return rc;
+        if (stopped) break;
+    }
+    if (stats) {
+        stats->steps = h->steps;
+        stats->sum_active = h->sum_active;
+        stats->t_ticks = h->t_ticks;
+    }
+    return NBODY_OK;
+}
+
+int nbody_hermite_get_state(nbody_hermite* h, hipStream_t st, nbody_src P, double* ax, double* ay,
+                            double* az, double* jx, double* jy, double* jz, int64_t* t, int64_t* dt) {
+    if (!h) return NBODY_ERR_ARG;
+    nbody_ctx* c = h->ctx;
+    if (!h->has_state) return set_err(c, NBODY_ERR_STATE, "hermite: no state");
+    DeviceGuard g(c->device);
+    const size_t b = sizeof(double) * (size_t)h->n;
+    const void* src[15] = {h->s[0], h->s[1], h->s[2], h->s[3], h->s[4], h->s[5], h->s[12], h->s[6],
+                           h->s[7], h->s[8], h->s[9], h->s[10], h->s[11], h->t, h->dt};
+    void* dst[15] = {(void*)P.x, (void*)P.y, (void*)P.z, (void*)P.vx, (void*)P.vy, (void*)P.vz,
+                     (void*)P.m, ax, ay, az, jx, jy, jz, t, dt};
+    for (int k = 0; k < 15; ++k) {
+        if (!dst[k]) continue;
+        hipError_t e = hipMemcpyAsync(dst[k], src[k], b, hipMemcpyDeviceToDevice, st);
+        if (e != hipSuccess) return hip_err(c, e, "state copy out");
+    }
+    return NBODY_OK;
+}
+
+int nbody_hermite_energy(nbody_hermite* h, hipStream_t st, double* ekin, double* epot) {
+    if (!h) return NBODY_ERR_ARG;
+    nbody_ctx* c = h->ctx;
+    if (!ekin || !epot) return set_err(c, NBODY_ERR_ARG, "ekin and epot must be host pointers");
+    if (!h->has_state) return set_err(c, NBODY_ERR_STATE, "hermite: no state");
+    DeviceGuard g(c->device);
+    const int n = (int)h->n;
+    const double* s[12];
+    for (int k = 0; k < 12; ++k) s[k] = h->s[k];
+    hipError_t e = launch_predict_all(n, s, h->t, h->tnow, h->pred, st);
+    if (e != hipSuccess) return hip_err(c, e, "predict launch");
+    nbody_src P;
+    P.x = h->pred[0]; P.y = h->pred[1]; P.z = h->pred[2];
+    P.vx = h->pred[3]; P.vy = h->pred[4]; P.vz = h->pred[5];
+    P.m = h->s[12];
+    const int p = (int)h->o.prec;
+    int rc = pack_rows(c, st, p, n, P, true, c->jpack);
+    if (rc) return rc;
+    double* o[7] = {h->f[0], h->f[1], h->f[2], h->f[3], h->f[4], h->f[5], h->f[6]};
+    rc = run_force(c, st, p, h->o.G, h->o.eps, n, (const float4*)c->jpack.p, nullptr, nullptr, 2, n,
+                   (const float4*)c->jpack.p, o, nullptr);
+    if (rc) return rc;
+    e = launch_energy(n, h->pred[3], h->pred[4], h->pred[5], h->s[12], h->f[6], h->e2, st);
+    if (e != hipSuccess) return hip_err(c, e, "energy launch");
+    double r[2];
+    e = hipMemcpyAsync(r, h->e2, sizeof r, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_err(c, e, "energy readback");
+    *ekin = r[0];
+    *epot = r[1];
+    return NBODY_OK;
+}
+
+// Checkpoint layout: header (n, t_ticks, steps, sum_active), then 13 float64
+// rows (x y z vx vy vz ax ay az jx jy jz m), then t and dt int64 rows.
+int64_t nbody_hermite_state_bytes(const nbody_hermite* h) {
+    if (!h) return 0;
+    return (int64_t)(4 * sizeof(int64_t) + (13 * sizeof(double) + 2 * sizeof(int64_t)) * (size_t)h->n);
+}
+
+int nbody_hermite_save(nbody_hermite* h, hipStream_t st, void* buf) {
+    if (!h) return NBODY_ERR_ARG;
+    nbody_ctx* c = h->ctx;
+    if (!buf) return set_err(c, NBODY_ERR_ARG, "NULL buffer");
+    if (!h->has_state) return set_err(c, NBODY_ERR_STATE, "hermite: no state");
+    DeviceGuard g(c->device);
+    int64_t* hdr = (int64_t*)buf;
+    hdr[0] = h->n;
+    hdr[1] = h->t_ticks;
+    hdr[2] = h->steps;
+    hdr[3] = h->sum_active;
+    char* p = (char*)buf + 4 * sizeof(int64_t);
+    const size_t b = sizeof(double) * (size_t)h->n;
+    for (int k = 0; k < 13; ++k, p += b) {
+        hipError_t e = hipMemcpyAsync(p, h->s[k], b, hipMemcpyDeviceToHost, st);
+        if (e != hipSuccess) return hip_err(c, e, "save copy");
+    }
+    hipError_t e = hipMemcpyAsync(p, h->t, b, hipMemcpyDeviceToHost, st);
+    p += b;
+    if (e == hipSuccess) e = hipMemcpyAsync(p, h->dt, b, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_err(c, e, "save copy");
+    return NBODY_OK;
+}
+
+int nbody_hermite_load(nbody_hermite* h, hipStream_t st, const void* buf) {
+    if (!h) return NBODY_ERR_ARG;
+    nbody_ctx* c = h->ctx;
+    if (!buf) return set_err(c, NBODY_ERR_ARG, "NULL buffer");
+    const int64_t* hdr = (const int64_t*)buf;
+    if (hdr[0] != h->n) return set_err(c, NBODY_ERR_ARG, "checkpoint holds %lld particles, driver %lld",
+                                       (long long)hdr[0], (long long)h->n);
+    DeviceGuard g(c->device);
+    const char* p = (const char*)buf + 4 * sizeof(int64_t);
+    const size_t b = sizeof(double) * (size_t)h->n;
+    for (int k = 0; k < 13; ++k, p += b) {
+        hipError_t e = hipMemcpyAsync(h->s[k], p, b, hipMemcpyHostToDevice, st);
+        if (e != hipSuccess) return hip_err(c, e, "load copy");
+    }
+    hipError_t e = hipMemcpyAsync(h->t, p, b, hipMemcpyHostToDevice, st);
+    p += b;
+    if (e == hipSuccess) e = hipMemcpyAsync(h->dt, p, b, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(h->tnow, &hdr[1], sizeof(int64_t), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_err(c, e, "load copy");
+    h->t_ticks = hdr[1];
+    h->steps = hdr[2];
+    h->sum_active = hdr[3];
+    h->has_state = true;
+    return NBODY_OK;
+}
+
+int nbody_autotune(nbody_ctx* c, hipStream_t st, nbody_prec prec, double G, double eps, int64_t n_i,
+                   nbody_src I, int64_t n_j, nbody_src J, nbody_out out, int reps, nbody_tile* best,
+                   double* best_ms) {
+    if (!c) return NBODY_ERR_ARG;
+    if (int rc = check_common(c, prec, G, eps)) return rc;
+    if (n_i <= 0 || n_j <= 0 || n_i > kMaxN || n_j > kMaxN)
+        return set_err(c, NBODY_ERR_ARG, "autotune needs 1 <= n_i, n_j <= 2^31-1");
+    if (reps < 1 || reps > 100) return set_err(c, NBODY_ERR_ARG, "reps must be in [1, 100]");
+    if (int rc = check_src(c, I, false, "I")) return rc;
+    if (int rc = check_src(c, J, true, "J")) return rc;
+    if (int rc = check_out(c, out)) return rc;
+    if (int rc = need_device(c)) return rc;
+    DeviceGuard g(c->device);
+    const int p = (int)prec;
+    int rc = pack_rows(c, st, p, n_j, J, true, c->jpack);
+    if (rc) return rc;
+    const float4* ip = (const float4*)c->jpack.p;
+    if (!(n_i == n_j && same_src(I, J))) {
+        rc = pack_rows(c, st, p, n_i, I, false, c->ipack);
+        if (rc) return rc;
+        ip = (const float4*)c->ipack.p;
+    }
+    double* o[7] = {out.ax, out.ay, out.az, out.jx, out.jy, out.jz, out.pot};
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return set_err(c, NBODY_ERR_DEVICE, "event create");
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return set_err(c, NBODY_ERR_DEVICE, "event create");
+    }
+    const int tjs[3] = {64, 128, 256}, ipts[3] = {1, 2, 4}, wgs[2] = {128, 256};
+    nbody_tile bt{};
+    double bms = 1e300;
+    for (int a = 0; a < 3 && !rc; ++a)
+        for (int b = 0; b < 3 && !rc; ++b)
+            for (int w = 0; w < 2 && !rc; ++w) {
+                nbody_tile t{tjs[a], ipts[b], wgs[w], 0};
+                t.split = choose_split(n_i, n_j, t);
+                rc = run_force(c, st, p, G, eps, n_i, ip, nullptr, nullptr, 0, n_j, (const float4*)c->jpack.p, o, &t);
+                if (rc) break;
+                hipError_t e = hipEventRecord(e0, st);
+                for (int r = 0; r < reps && e == hipSuccess && !rc; ++r)
+                    rc = run_force(c, st, p, G, eps, n_i, ip, nullptr, nullptr, 0, n_j, (const float4*)c->jpack.p, o, &t);
+                if (rc) break;
+                if (e == hipSuccess) e = hipEventRecord(e1, st);
+                if (e == hipSuccess) e = hipEventSynchronize(e1);
+                float ms = 0.f;
+                if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+                if (e != hipSuccess) {
+                    rc = hip_err(c, e, "autotune timing");
+                    break;
+                }
+                const double per = (double)ms / reps;
+                if (per < bms) {
+                    bms = per;
+                    bt = t;
+                }
+            }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    c->tune.store(p, n_i, n_j, bt, bms);
+    if (!c->tune.save()) return set_err(c, NBODY_ERR_ARG, "cannot write tune cache %s", c->tune.path().c_str());
+    if (best) *best = bt;
+    if (best_ms) *best_ms = bms;
+    return NBODY_OK;
+}
+
+// Host copy of the step-level rule the corrector kernel applies (for
+// host-side checks of the integer rule; no device work).
+int64_t nbody_block_level(double crit, int64_t dt_old, int64_t t_new, int lmin, int lmax) {
+    if (lmin < -20 || lmax > 0 || lmin > lmax) return -1;
+    return block_level(crit, dt_old, t_new, lmin, lmax);
+}
+
+}  // extern "C"

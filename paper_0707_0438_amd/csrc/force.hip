@@ -1,0 +1,353 @@
+// Pairwise acceleration / jerk / potential kernel for gfx950 (CDNA4).
+//
+// What is computed (Eq. 1 with Plummer softening, Section 3.3; jerk and
+// potential, Section 3): for each i of an i-list and every j of a j-set,
+//   r = x_j - x_i, u = v_j - v_i, s = r.r + eps^2, q = s^-1/2,
+//   a += m q^3 r,  jerk += m q^3 (u - 3 (r.u) q^2 r),  phi -= m q.
+//
+// Scheme (the tile scheme of Section 3.1 and Fig. 1, re-laid for CDNA4):
+//  * each lane keeps IPT i-particles in registers for the whole j sweep;
+//  * the work-group stages j records tile by tile in LDS (double buffered,
+//    one barrier per tile); every lane then reads each record with a
+//    wave-uniform (broadcast) LDS load;
+//  * float32 VALU arithmetic with one hardware v_rsq_f32 per pair, no
+//    branch in the loop (the ragged tail is padded with massless records
+//    far away); all N^2 pairs are visited, self included (Section 3.1):
+//    the self pair gives exactly 0 to a and jerk and its potential term is
+//    removed in the epilogue;
+//  * DS_COMP: positions are double-single and the relative coordinate is
+//    (x_j,hi - x_i,hi) + (x_j,lo - x_i,lo); per-tile float32 partial sums
+//    are folded into a two-sum (hi, lo) accumulator;
+//  * small i-lists: the j set is cut into S ranges handled by different
+//    work-groups that write (hi, lo) partials, reduced afterwards in
+//    float64 in fixed order (the j-split of Section 3.2, with the combine
+//    moved from the host to the device).
+#include "nbody_internal.h"
+
+namespace nb {
+
+constexpr float kPadPos = 1.0e18f;   // far-away position of padding records
+
+template <int PREC>
+struct Rec;
+template <>
+struct Rec<0> { static constexpr int R = kRecFP32; };
+template <>
+struct Rec<1> { static constexpr int R = kRecDS; };
+
+__device__ __forceinline__ void two_sum_fold(float& hi, float& lo, float p) {
+    // Knuth's TwoSum: hi + p = s + e exactly; the error joins lo.
+    const float s = hi + p;
+    const float bb = s - hi;
+    const float e = (hi - (s - bb)) + (p - bb);
+    hi = s;
+    lo += e;
+}
+
+template <int PREC, int IPT, int TJ, int WG, bool EPS0>
+__global__ __launch_bounds__(WG) void force_kernel(ForceArgs a) {
+    constexpr int R = Rec<PREC>::R;
+    constexpr int NE = TJ * R;                  // float4 per tile
+    constexpr int NLD = (NE + WG - 1) / WG;     // staging loads per lane
+    __shared__ float4 sh[2][NE];
+
+    const int tid = threadIdx.x;
+    const int ibase = blockIdx.x * (WG * IPT);
+    const int jb = blockIdx.y * a.jchunk;
+    const int je = min(a.nj, jb + a.jchunk);
+    const int ntiles = je > jb ? (je - jb + TJ - 1) / TJ : 0;
+
+    // i-particles of this lane
+    float ix[IPT], iy[IPT], iz[IPT], iu[IPT], iv[IPT], iw[IPT];
+    float lx[IPT], ly[IPT], lz[IPT];
+#pragma unroll
+    for (int k = 0; k < IPT; ++k) {
+        const int ii = ibase + k * WG + tid;
+        float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f), r1 = r0, r2 = r0;
+        if (ii < a.ni) {
+            const int src = a.iidx ? a.iidx[ii] : ii;
+            r0 = a.ipack[(size_t)src * R + 0];
+            r1 = a.ipack[(size_t)src * R + 1];
+            if (PREC == 1) r2 = a.ipack[(size_t)src * R + 2];
+        }
+        ix[k] = r0.x; iy[k] = r0.y; iz[k] = r0.z;
+        iu[k] = r1.x; iv[k] = r1.y; iw[k] = r1.z;
+        lx[k] = r2.x; ly[k] = r2.y; lz[k] = r2.z;
+    }
+
+    float acc[IPT][7];
+    float chi[IPT][7], clo[IPT][7];
+#pragma unroll
+    for (int k = 0; k < IPT; ++k)
+#pragma unroll
+        for (int q = 0; q < 7; ++q) { acc[k][q] = 0.f; chi[k][q] = 0.f; clo[k][q] = 0.f; }
+
+    float4 stg[NLD];
+    auto load_tile = [&](int t) {
+        const int j0 = jb + t * TJ;
+#pragma unroll
+        for (int q = 0; q < NLD; ++q) {
+            const int e = tid + q * WG;
+            if (e < NE) {
+                const int jj = e / R;
+                const int c = e - jj * R;
+                if (j0 + jj < je)
+                    stg[q] = a.jpack[(size_t)j0 * R + e];
+                else
+                    stg[q] = c == 0 ? make_float4(kPadPos, kPadPos, kPadPos, 0.f)
+                                    : make_float4(0.f, 0.f, 0.f, 0.f);
+            }
+        }
+    };
+    auto store_tile = [&](int buf) {
+#pragma unroll
+        for (int q = 0; q < NLD; ++q) {
+            const int e = tid + q * WG;
+            if (e < NE) sh[buf][e] = stg[q];
+        }
+    };
+
+    const float eps2 = a.eps2;
+    if (ntiles > 0) {
+        load_tile(0);
+        store_tile(0);
+    }
+    __syncthreads();
+
+    for (int t = 0; t < ntiles; ++t) {
+        const int buf = t & 1;
+        if (t + 1 < ntiles) load_tile(t + 1);
+        const float4* tile = sh[buf];
+#pragma unroll 4
+        for (int jj = 0; jj < TJ; ++jj) {
+            const float4 q0 = tile[jj * R + 0];
+            const float4 q1 = tile[jj * R + 1];
+            float4 q2;
+            if (PREC == 1) q2 = tile[jj * R + 2];
+#pragma unroll
+            for (int k = 0; k < IPT; ++k) {
+                float dx, dy, dz;
+                if (PREC == 1) {
+                    dx = (q0.x - ix[k]) + (q2.x - lx[k]);
+                    dy = (q0.y - iy[k]) + (q2.y - ly[k]);
+                    dz = (q0.z - iz[k]) + (q2.z - lz[k]);
+                } else {
+                    dx = q0.x - ix[k];
+                    dy = q0.y - iy[k];
+                    dz = q0.z - iz[k];
+                }
+                const float ux = q1.x - iu[k], uy = q1.y - iv[k], uz = q1.z - iw[k];
+                const float s = fmaf(dz, dz, fmaf(dy, dy, fmaf(dx, dx, eps2)));
+                const float rv = fmaf(dz, uz, fmaf(dy, uy, dx * ux));
+                float rinv = __builtin_amdgcn_rsqf(s);
+                if (EPS0) rinv = s > 0.f ? rinv : 0.f;
+                const float rinv2 = rinv * rinv;
+                const float mr = q0.w * rinv;
+                const float mr3 = mr * rinv2;
+                const float al = 3.0f * rv * rinv2;
+                acc[k][0] = fmaf(mr3, dx, acc[k][0]);
+                acc[k][1] = fmaf(mr3, dy, acc[k][1]);
+                acc[k][2] = fmaf(mr3, dz, acc[k][2]);
+                acc[k][3] = fmaf(mr3, fmaf(-al, dx, ux), acc[k][3]);
+                acc[k][4] = fmaf(mr3, fmaf(-al, dy, uy), acc[k][4]);
+                acc[k][5] = fmaf(mr3, fmaf(-al, dz, uz), acc[k][5]);
+                acc[k][6] += mr;
+            }
+        }
+        if (PREC == 1) {
+#pragma unroll
+            for (int k = 0; k < IPT; ++k)
+#pragma unroll
+                for (int q = 0; q < 7; ++q) {
+                    two_sum_fold(chi[k][q], clo[k][q], acc[k][q]);
+                    acc[k][q] = 0.f;
+                }
+        }
+        if (t + 1 < ntiles) store_tile(buf ^ 1);
+        __syncthreads();
+    }
+
+    // epilogue
+#pragma unroll
+    for (int k = 0; k < IPT; ++k) {
+        const int ii = ibase + k * WG + tid;
+        if (ii >= a.ni) continue;
+        float hi[7], lo[7];
+#pragma unroll
+        for (int q = 0; q < 7; ++q) {
+            hi[q] = PREC == 1 ? chi[k][q] : acc[k][q];
+            lo[q] = PREC == 1 ? clo[k][q] : 0.f;
+        }
+        if (a.partial) {
+            const size_t base = (size_t)blockIdx.y * 7 * a.ni + ii;
+#pragma unroll
+            for (int q = 0; q < 7; ++q) a.part[base + (size_t)q * a.ni] = make_float2(hi[q], lo[q]);
+        } else {
+            double pot = (double)hi[6] + (double)lo[6];
+            if (!EPS0) {
+                const int self = self_index(a.self_mode, a.iidx, a.iself, ii);
+                if (self >= 0 && self < a.nj) {
+                    // remove exactly the float32 term the loop added for j = i
+                    const float ms = a.jpack[(size_t)self * R].w;
+                    pot -= (double)(ms * __builtin_amdgcn_rsqf(eps2));
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < 6; ++q) a.out[q][ii] = a.G * ((double)hi[q] + (double)lo[q]);
+            a.out[6][ii] = -a.G * pot;
+        }
+    }
+}
+
+// Float64 reduction of split partials in fixed order s = 0 .. S-1, then the
+// self-potential removal and the factor G.
+__global__ __launch_bounds__(256) void reduce_kernel(ReduceArgs a) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.ni) return;
+    double v[7];
+#pragma unroll
+    for (int q = 0; q < 7; ++q) {
+        double s = 0.0;
+        for (int sp = 0; sp < a.S; ++sp) {
+            const float2 p = a.part[((size_t)sp * 7 + q) * a.ni + i];
+            s += (double)p.x;
+            s += (double)p.y;
+        }
+        v[q] = s;
+    }
+    if (!a.eps0) {
+        const int self = self_index(a.self_mode, a.iidx, a.iself, i);
+        if (self >= 0 && self < a.nj) {
+            const int R = a.prec == 0 ? kRecFP32 : kRecDS;
+            const float ms = a.jpack[(size_t)self * R].w;
+            v[6] -= (double)(ms * __builtin_amdgcn_rsqf(a.eps2));
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 6; ++q) a.out[q][i] = a.G * v[q];
+    a.out[6][i] = -a.G * v[6];
+}
+
+hipError_t launch_reduce(const ReduceArgs& a, hipStream_t st) {
+    if (a.ni <= 0) return hipSuccess;
+    hipLaunchKernelGGL(reduce_kernel, dim3((a.ni + 255) / 256), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+template <int PREC>
+__global__ __launch_bounds__(256) void pack_kernel(PackArgs a) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= a.n) return;
+    double px = a.x[k], py = a.y[k], pz = a.z[k];
+    double qx = a.vx[k], qy = a.vy[k], qz = a.vz[k];
+    if (a.t) {
+        const double D = (double)(*a.tnext - a.t[k]) * kTick;
+        predict1(px, qx, a.ax[k], a.jx[k], D, px, qx);
+        predict1(py, qy, a.ay[k], a.jy[k], D, py, qy);
+        predict1(pz, qz, a.az[k], a.jz[k], D, pz, qz);
+    }
+    const float m = a.m ? (float)a.m[k] : 0.f;
+    if (PREC == 0) {
+        a.out[2 * (size_t)k] = make_float4((float)px, (float)py, (float)pz, m);
+        a.out[2 * (size_t)k + 1] = make_float4((float)qx, (float)qy, (float)qz, 0.f);
+    } else {
+        const float hx = (float)px, hy = (float)py, hz = (float)pz;
+        const float lx = (float)(px - (double)hx), ly = (float)(py - (double)hy),
+                    lz = (float)(pz - (double)hz);
+        a.out[3 * (size_t)k] = make_float4(hx, hy, hz, m);
+        a.out[3 * (size_t)k + 1] = make_float4((float)qx, (float)qy, (float)qz, 0.f);
+        a.out[3 * (size_t)k + 2] = make_float4(lx, ly, lz, 0.f);
+    }
+}
+
+hipError_t launch_pack(const PackArgs& a, hipStream_t st) {
+    if (a.n <= 0) return hipSuccess;
+    const dim3 g((a.n + 255) / 256), b(256);
+    if (a.prec == 0)
+        hipLaunchKernelGGL(pack_kernel<0>, g, b, 0, st, a);
+    else
+        hipLaunchKernelGGL(pack_kernel<1>, g, b, 0, st, a);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void predict_all_kernel(int n, const double* __restrict__ x,
+                                                          const double* __restrict__ y,
+                                                          const double* __restrict__ z,
+                                                          const double* __restrict__ vx,
+                                                          const double* __restrict__ vy,
+                                                          const double* __restrict__ vz,
+                                                          const double* __restrict__ ax,
+                                                          const double* __restrict__ ay,
+                                                          const double* __restrict__ az,
+                                                          const double* __restrict__ jx,
+                                                          const double* __restrict__ jy,
+                                                          const double* __restrict__ jz,
+                                                          const int64_t* __restrict__ t,
+                                                          const int64_t* __restrict__ tnext,
+                                                          double* ox, double* oy, double* oz,
+                                                          double* ovx, double* ovy, double* ovz) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const double D = (double)(*tnext - t[k]) * kTick;
+    predict1(x[k], vx[k], ax[k], jx[k], D, ox[k], ovx[k]);
+    predict1(y[k], vy[k], ay[k], jy[k], D, oy[k], ovy[k]);
+    predict1(z[k], vz[k], az[k], jz[k], D, oz[k], ovz[k]);
+}
+
+hipError_t launch_predict_all(int n, const double* const* s, const int64_t* t, const int64_t* tnext,
+                              double* const* o, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(predict_all_kernel, dim3((n + 255) / 256), dim3(256), 0, st, n, s[0], s[1],
+                       s[2], s[3], s[4], s[5], s[6], s[7], s[8], s[9], s[10], s[11], t, tnext, o[0],
+                       o[1], o[2], o[3], o[4], o[5]);
+    return hipGetLastError();
+}
+
+// ---- variant table -----------------------------------------------------------
+
+template <int PREC, int IPT, int TJ, int WG, bool EPS0>
+static hipError_t launch_one(int nb, int S, const ForceArgs& a, hipStream_t st) {
+    hipLaunchKernelGGL((force_kernel<PREC, IPT, TJ, WG, EPS0>), dim3(nb, S), dim3(WG), 0, st, a);
+    return hipGetLastError();
+}
+
+typedef hipError_t (*LaunchFn)(int, int, const ForceArgs&, hipStream_t);
+
+struct Variant {
+    int prec, ipt, tj, wg;
+    bool eps0;
+    LaunchFn fn;
+};
+
+#define NB_V(P, I, T, W, E) {P, I, T, W, E, &launch_one<P, I, T, W, E>}
+#define NB_VT(P, I, W)                                                                  \
+    NB_V(P, I, 64, W, false), NB_V(P, I, 128, W, false), NB_V(P, I, 256, W, false)
+#define NB_VW(P, I) NB_VT(P, I, 128), NB_VT(P, I, 256)
+#define NB_VP(P) NB_VW(P, 1), NB_VW(P, 2), NB_VW(P, 4)
+
+static const Variant kVariants[] = {
+    NB_VP(0),
+    NB_VP(1),
+    // unsoftened (eps = 0) path: one shape per precision
+    NB_V(0, 1, 128, 256, true), NB_V(0, 2, 128, 256, true),
+    NB_V(1, 1, 128, 256, true), NB_V(1, 2, 128, 256, true),
+};
+
+static const Variant* find_variant(int prec, int ipt, int tj, int wg, bool eps0) {
+    for (const Variant& v : kVariants)
+        if (v.prec == prec && v.ipt == ipt && v.tj == tj && v.wg == wg && v.eps0 == eps0) return &v;
+    return nullptr;
+}
+
+bool force_variant_exists(int prec, int ipt, int tj, int wg, bool eps0) {
+    return find_variant(prec, ipt, tj, wg, eps0) != nullptr;
+}
+
+hipError_t launch_force(int prec, int ipt, int tj, int wg, bool eps0, int nb, int S,
+                        const ForceArgs& a, hipStream_t st) {
+    const Variant* v = find_variant(prec, ipt, tj, wg, eps0);
+    if (!v) return hipErrorInvalidValue;
+    return v->fn(nb, S, a, st);
+}
+
+}  // namespace nb

@@ -1,0 +1,206 @@
+// Block time-step kernels (Section 3 and 3.1): active-block selection on
+// integer ticks, the float64 Hermite corrector with the Aarseth step
+// criterion and power-of-two step levels, first steps, and energy sums.
+#include "nbody_internal.h"
+
+namespace nb {
+
+constexpr int kSelThreads = 1024;
+constexpr int kSelWaves = kSelThreads / 64;
+
+// One work-group scans the whole (t, dt) array: first the minimum of
+// t + dt, then an order-preserving compaction of the indices that reach it.
+// Integer work only, so the result is exact.
+__global__ __launch_bounds__(kSelThreads) void select_kernel(int n, const int64_t* __restrict__ t,
+                                                             const int64_t* __restrict__ dt,
+                                                             int32_t* __restrict__ idx,
+                                                             int64_t* __restrict__ out2) {
+    __shared__ int64_t red[kSelWaves];
+    __shared__ int wsum[kSelWaves];
+    __shared__ int64_t tn_sh;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+
+    int64_t m = INT64_MAX;
+    for (int k = tid; k < n; k += kSelThreads) {
+        const int64_t v = t[k] + dt[k];
+        m = v < m ? v : m;
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        const int64_t o = __shfl_xor(m, off);
+        m = o < m ? o : m;
+    }
+    if (lane == 0) red[w] = m;
+    __syncthreads();
+    if (tid == 0) {
+        int64_t r = red[0];
+        for (int k = 1; k < kSelWaves; ++k) r = red[k] < r ? red[k] : r;
+        tn_sh = r;
+    }
+    __syncthreads();
+    const int64_t tn = tn_sh;
+
+    // compaction in chunks of 4 * kSelThreads consecutive elements; each lane
+    // owns 4 consecutive entries so the output stays in ascending order
+    int base = 0;
+    for (int c0 = 0; c0 < n; c0 += 4 * kSelThreads) {
+        const int k0 = c0 + 4 * tid;
+        int f[4], cnt = 0;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int k = k0 + u;
+            f[u] = (k < n && t[k] + dt[k] == tn) ? 1 : 0;
+            cnt += f[u];
+        }
+        // inclusive scan of cnt across the wave
+        int incl = cnt;
+        for (int off = 1; off < 64; off <<= 1) {
+            const int o = __shfl_up(incl, off);
+            if (lane >= off) incl += o;
+        }
+        if (lane == 63) wsum[w] = incl;
+        __syncthreads();
+        int wbase = 0, total = 0;
+        for (int k = 0; k < kSelWaves; ++k) {
+            const int s = wsum[k];
+            wbase += k < w ? s : 0;
+            total += s;
+        }
+        int pos = base + wbase + incl - cnt;
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (f[u]) idx[pos++] = k0 + u;
+        base += total;
+        __syncthreads();   // wsum is rewritten by the next chunk
+    }
+    if (tid == 0) {
+        out2[0] = base;
+        out2[1] = tn;
+    }
+}
+
+hipError_t launch_select(int n, const int64_t* t, const int64_t* dt, int32_t* idx, int64_t* out2,
+                         hipStream_t st) {
+    hipLaunchKernelGGL(select_kernel, dim3(1), dim3(kSelThreads), 0, st, n, t, dt, idx, out2);
+    return hipGetLastError();
+}
+
+__device__ __forceinline__ double norm3(double a, double b, double c) { return sqrt(a * a + b * b + c * c); }
+
+// Corrector for the active block (Makino & Aarseth 1992 Hermite scheme):
+// with D = dt_i, the predicted state recomputed exactly as in the pack,
+//   a2 = (-6 (a0 - a1) - D (4 j0 + 2 j1)) / D^2
+//   a3 = (12 (a0 - a1) + 6 D (j0 + j1)) / D^3
+//   x1 = x_p + a2 D^4/24 + a3 D^5/120,  v1 = v_p + a2 D^3/6 + a3 D^4/24,
+// then the Aarseth criterion with a2 carried to the new time, and the
+// power-of-two level rule.
+__global__ __launch_bounds__(256) void correct_kernel(CorrectArgs a) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= a.n_act) return;
+    const int i = a.idx[c];
+    const int64_t tn = *a.tnext;
+    const double D = (double)a.dt[i] * kTick;
+    double* X[3] = {a.x, a.y, a.z};
+    double* V[3] = {a.vx, a.vy, a.vz};
+    double* A[3] = {a.ax, a.ay, a.az};
+    double* J[3] = {a.jx, a.jy, a.jz};
+    const double Dp = (double)(tn - a.t[i]) * kTick;   // equals D for an active particle
+    double a1[3], j1[3], a2[3], a3[3];
+    const double iD = 1.0 / D, iD2 = iD * iD, iD3 = iD2 * iD;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        double xp, vp;
+        predict1(X[k][i], V[k][i], A[k][i], J[k][i], Dp, xp, vp);
+        a1[k] = a.f[k][c];
+        j1[k] = a.f[3 + k][c];
+        const double a0 = A[k][i], j0 = J[k][i];
+        const double da = a0 - a1[k];
+        a2[k] = (-6.0 * da - D * (4.0 * j0 + 2.0 * j1[k])) * iD2;
+        a3[k] = (12.0 * da + 6.0 * D * (j0 + j1[k])) * iD3;
+        const double D2 = D * D, D3 = D2 * D, D4 = D3 * D;
+        X[k][i] = xp + D4 * (a2[k] * (1.0 / 24.0) + D * a3[k] * (1.0 / 120.0));
+        V[k][i] = vp + D3 * (a2[k] * (1.0 / 6.0) + D * a3[k] * (1.0 / 24.0));
+        A[k][i] = a1[k];
+        J[k][i] = j1[k];
+    }
+    a.t[i] = tn;
+    if (!a.shared) {
+        const double b0 = a2[0] + a3[0] * D, b1 = a2[1] + a3[1] * D, b2 = a2[2] + a3[2] * D;
+        const double na = norm3(a1[0], a1[1], a1[2]), nj = norm3(j1[0], j1[1], j1[2]);
+        const double n2 = norm3(b0, b1, b2), n3 = norm3(a3[0], a3[1], a3[2]);
+        const double crit = sqrt(a.eta * (na * n2 + nj * nj) / (nj * n3 + n2 * n2));
+        a.dt[i] = block_level(crit, a.dt[i], tn, a.lmin, a.lmax);
+    }
+}
+
+hipError_t launch_correct(const CorrectArgs& a, hipStream_t st) {
+    if (a.n_act <= 0) return hipSuccess;
+    hipLaunchKernelGGL(correct_kernel, dim3((a.n_act + 255) / 256), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void init_dt_kernel(InitDtArgs a) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.n) return;
+    if (a.shared_log2 != 0) {
+        a.dt[i] = (int64_t)1 << (a.shared_log2 + 20);
+        return;
+    }
+    const double na = norm3(a.ax[i], a.ay[i], a.az[i]);
+    const double nj = norm3(a.jx[i], a.jy[i], a.jz[i]);
+    a.dt[i] = block_level(a.eta_s * na / nj, 0, 0, a.lmin, a.lmax);
+}
+
+hipError_t launch_init_dt(const InitDtArgs& a, hipStream_t st) {
+    if (a.n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(init_dt_kernel, dim3((a.n + 255) / 256), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+// Energy sums in float64 by one work-group in a fixed order (deterministic).
+__global__ __launch_bounds__(1024) void energy_kernel(int n, const double* __restrict__ vx,
+                                                      const double* __restrict__ vy,
+                                                      const double* __restrict__ vz,
+                                                      const double* __restrict__ m,
+                                                      const double* __restrict__ pot,
+                                                      double* __restrict__ out2) {
+    __shared__ double sk[1024], sp[1024];
+    const int tid = threadIdx.x;
+    double k = 0.0, p = 0.0;
+    for (int i = tid; i < n; i += 1024) {
+        k += 0.5 * m[i] * (vx[i] * vx[i] + vy[i] * vy[i] + vz[i] * vz[i]);
+        p += 0.5 * m[i] * pot[i];
+    }
+    sk[tid] = k;
+    sp[tid] = p;
+    __syncthreads();
+    for (int s = 512; s > 0; s >>= 1) {
+        if (tid < s) {
+            sk[tid] += sk[tid + s];
+            sp[tid] += sp[tid + s];
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        out2[0] = sk[0];
+        out2[1] = sp[0];
+    }
+}
+
+hipError_t launch_energy(int n, const double* vx, const double* vy, const double* vz, const double* m,
+                         const double* pot, double* out2, hipStream_t st) {
+    hipLaunchKernelGGL(energy_kernel, dim3(1), dim3(1024), 0, st, n, vx, vy, vz, m, pot, out2);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void fill_i64_kernel(int64_t* p, int n, int64_t v) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+hipError_t launch_fill_i64(int64_t* p, int n, int64_t v, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_i64_kernel, dim3((n + 255) / 256), dim3(256), 0, st, p, n, v);
+    return hipGetLastError();
+}
+
+}  // namespace nb

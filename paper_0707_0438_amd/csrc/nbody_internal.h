@@ -1,0 +1,142 @@
+// Internal declarations shared by the kernel and host translation units of
+// libnbody.  Not installed; the public interface is include/nbody.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace nb {
+
+// One tick of integer time is 2^-20 N-body time units; block steps are
+// powers of two between 2^-20 and 2^0, so every block time is an exact
+// integer number of ticks.
+constexpr double kTick = 1.0 / 1048576.0;
+constexpr int kTickLog2 = -20;
+
+// Packed particle records (float4 units).
+//  FP32 : {x, y, z, m}, {vx, vy, vz, 0}
+//  DS   : {x_hi, y_hi, z_hi, m}, {vx, vy, vz, 0}, {x_lo, y_lo, z_lo, 0}
+constexpr int kRecFP32 = 2;
+constexpr int kRecDS = 3;
+inline int rec_words(int prec) { return prec == 0 ? kRecFP32 : kRecDS; }
+
+// Arguments of the pairwise kernel (passed by value).
+struct ForceArgs {
+    const float4* ipack;    // i records
+    const int32_t* iidx;    // i -> record index in ipack (NULL: identity)
+    int ni;
+    const float4* jpack;    // j records
+    int nj;
+    int jchunk;             // j per split (multiple of the tile)
+    float eps2;             // eps^2 rounded to float
+    int partial;            // 0: final float64 outputs, 1: write split partials
+    double G;
+    const int32_t* iself;   // self j index per i (used when self_mode == 0; NULL: none)
+    int self_mode;          // 0: iself[i], 1: iidx[i], 2: i itself
+    double* out[7];         // ax ay az jx jy jz pot (final mode)
+    float2* part;           // [S][7][ni] (hi, lo) partials (partial mode)
+};
+
+struct ReduceArgs {
+    int ni, nj, S, prec, eps0;
+    const float2* part;
+    const float4* jpack;
+    const int32_t* iidx;
+    const int32_t* iself;
+    int self_mode;
+    float eps2;
+    double G;
+    double* out[7];
+};
+
+// Launch the pairwise kernel for one configuration; returns hipError_t.
+hipError_t launch_force(int prec, int ipt, int tile_j, int wg, bool eps0, int n_iblocks, int S,
+                        const ForceArgs& a, hipStream_t st);
+bool force_variant_exists(int prec, int ipt, int tile_j, int wg, bool eps0);
+hipError_t launch_reduce(const ReduceArgs& a, hipStream_t st);
+
+// Pack float64 rows into records; with t != NULL every particle is first
+// predicted to the block time *tnext (device) by the Hermite predictor.
+struct PackArgs {
+    int n, prec;
+    const double *x, *y, *z, *vx, *vy, *vz, *m;
+    const double *ax, *ay, *az, *jx, *jy, *jz;   // predictor inputs (or NULL)
+    const int64_t* t;                              // ticks (or NULL: no prediction)
+    const int64_t* tnext;                          // device scalar
+    float4* out;
+};
+hipError_t launch_pack(const PackArgs& a, hipStream_t st);
+
+// Active-block selection: out2[0] = n_act, out2[1] = t_next.
+hipError_t launch_select(int n, const int64_t* t, const int64_t* dt, int32_t* idx, int64_t* out2,
+                         hipStream_t st);
+
+struct CorrectArgs {
+    int n_act;
+    const int32_t* idx;
+    const int64_t* tnext;             // device scalar
+    double *x, *y, *z, *vx, *vy, *vz;
+    double *ax, *ay, *az, *jx, *jy, *jz;
+    int64_t *t, *dt;
+    const double* f[6];               // new a (3) and jerk (3) of the block, [n_act]
+    double eta;
+    int lmin, lmax, shared;           // shared != 0: keep dt
+};
+hipError_t launch_correct(const CorrectArgs& a, hipStream_t st);
+
+// First steps after the initial force evaluation.
+struct InitDtArgs {
+    int n;
+    const double *ax, *ay, *az, *jx, *jy, *jz;
+    int64_t *t, *dt;
+    double eta_s;
+    int lmin, lmax, shared_log2;
+};
+hipError_t launch_init_dt(const InitDtArgs& a, hipStream_t st);
+
+// Deterministic float64 sums: out[0] = sum 0.5 m v^2, out[1] = sum 0.5 m pot.
+hipError_t launch_energy(int n, const double* vx, const double* vy, const double* vz,
+                         const double* m, const double* pot, double* out2, hipStream_t st);
+
+// p[0 .. n-1] = v (a kernel, so that graph capture records no memset node)
+hipError_t launch_fill_i64(int64_t* p, int n, int64_t v, hipStream_t st);
+
+// Predict every particle to *tnext in float64 (energy diagnostics).
+hipError_t launch_predict_all(int n, const double* const* state /*x y z vx vy vz ax ay az jx jy jz*/,
+                              const int64_t* t, const int64_t* tnext, double* const* outxv,
+                              hipStream_t st);
+
+// Hermite predictor (float64), Horner form of
+//   x_p = x + v D + a D^2/2 + j D^3/6,  v_p = v + a D + j D^2/2.
+__device__ __forceinline__ void predict1(double x, double v, double ac, double jk, double D,
+                                         double& xp, double& vp) {
+    xp = x + D * (v + D * (0.5 * ac + D * (jk * (1.0 / 6.0))));
+    vp = v + D * (ac + D * (0.5 * jk));
+}
+
+// j index of the particle that i-slot `ii` is (or -1): see ForceArgs::self_mode.
+__device__ __forceinline__ int self_index(int mode, const int32_t* iidx, const int32_t* iself, int ii) {
+    if (mode == 1) return iidx[ii];
+    if (mode == 2) return ii;
+    return iself ? iself[ii] : -1;
+}
+
+// Step-level rule shared by the corrector kernel and the host API.
+__host__ __device__ inline int64_t block_level(double crit, int64_t dt_old, int64_t t_new, int lmin,
+                                               int lmax) {
+    const int64_t dmin = (int64_t)1 << (lmin + 20);
+    const int64_t dmax = (int64_t)1 << (lmax + 20);
+    int64_t q = dmin;
+    // crit must be a positive finite number; otherwise the smallest level.
+    if (crit > 0.0 && crit <= 1.0e300) {
+        // largest power of two (in ticks) not above crit, within [dmin, dmax]
+        const double c_ticks = crit * 1048576.0;
+        while (q < dmax && (double)(q << 1) <= c_ticks) q <<= 1;
+    }
+    if (dt_old <= 0) return q;
+    if (q < dt_old) return q;
+    if (q > dt_old && (dt_old << 1) <= dmax && (t_new % (dt_old << 1)) == 0) return dt_old << 1;
+    return dt_old;
+}
+
+}  // namespace nb

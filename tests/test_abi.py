@@ -1,0 +1,146 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every function include/nbody.h declares, rejects bad arguments with the
+documented codes before touching a device, and its host copy of the block
+step rule is bit-exact against the oracle's integer rule."""
+import json
+import math
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_0707_0438_amd as nb
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "nbody.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(nbody_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_header_declarations_match_binding_list():
+    assert declared_functions() == sorted(nb.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    out = subprocess.run(["nm", "-D", "--defined-only", nb.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    syms = {ln.split()[-1] for ln in out.splitlines() if " T " in ln}
+    missing = [f for f in declared_functions() if f not in syms]
+    assert not missing, missing
+    L = nb.lib()
+    for f in declared_functions():
+        assert hasattr(L, f)
+    assert L.nbody_abi_version() == 1
+
+
+@pytest.fixture()
+def hostctx():
+    c = nb.Context(-1)
+    yield c
+    c.close()
+
+
+def _src(p=8):
+    return nb.Src(*([p] * 7))
+
+
+def _out(p=8):
+    return nb.Out(*([p] * 7))
+
+
+def test_force_argument_errors(hostctx):
+    L = nb.lib()
+    h = hostctx.handle
+    call = lambda **kw: L.nbody_force(h, None, kw.get("prec", 1), kw.get("G", 1.0), kw.get("eps", 0.1),
+                                      kw.get("ni", 10), kw.get("I", _src()), kw.get("iself"),
+                                      kw.get("nj", 10), kw.get("J", _src()), kw.get("out", _out()))
+    assert call(ni=-1) == -1
+    assert call(nj=-1) == -1
+    assert call(ni=1 << 31) == -1
+    assert call(eps=-0.5) == -1
+    assert call(eps=float("nan")) == -1
+    assert call(eps=float("inf")) == -1
+    assert call(G=float("inf")) == -1
+    assert call(prec=7) == -1
+    bad = _src(); bad.vz = None
+    assert call(I=bad) == -1
+    assert "row 5 is NULL" in hostctx.last_error()
+    mis = _src(); mis.y = 12
+    assert call(J=mis) == -1
+    assert "aligned" in hostctx.last_error()
+    nom = _src(); nom.m = None
+    assert call(J=nom) == -1                  # j masses are required
+    assert call(I=nom) == -4                  # i masses are not: reaches the device check
+    o = _out(); o.pot = None
+    assert call(out=o) == -1
+    assert call(ni=3, nj=0, iself=8) == -1    # self indices into an empty j set
+    # well-formed call on a context without a device
+    assert call() == -4
+    assert "no device" in hostctx.last_error()
+
+
+def test_other_entry_points_validate(hostctx):
+    L = nb.lib()
+    h = hostctx.handle
+    import ctypes as C
+    na, tn = C.c_int64(), C.c_int64()
+    assert L.nbody_select_active(h, None, -1, 8, 8, 8, C.byref(na), C.byref(tn)) == -1
+    assert L.nbody_select_active(h, None, 5, None, 8, 8, C.byref(na), C.byref(tn)) == -1
+    assert L.nbody_select_active(h, None, 5, 8, 8, 8, None, C.byref(tn)) == -1
+    assert L.nbody_reserve(h, -5, 1) == -1
+    t = nb.Tile(100, 2, 256, 0)
+    assert L.nbody_set_tile(h, 1, C.byref(t)) == -1
+    t = nb.Tile(128, 3, 256, 0)
+    assert L.nbody_set_tile(h, 1, C.byref(t)) == -1
+    t = nb.Tile(128, 2, 256, 0)
+    assert L.nbody_set_tile(h, 1, C.byref(t)) == 0
+    assert hostctx.get_tile(1000, 1000) == {"tile_j": 128, "ipt": 2, "wg": 256,
+                                            "split": hostctx.get_tile(1000, 1000)["split"]}
+    assert L.nbody_set_tile(h, 1, None) == 0
+    hp = C.c_void_p()
+    o = nb.HermiteOpts(1.0, 0.01, 0.02, 0.01, -20, -3, 0, 1)
+    assert L.nbody_hermite_create(h, C.byref(hp), 0, C.byref(o)) == -1
+    o2 = nb.HermiteOpts(1.0, 0.01, 0.02, 0.01, -3, -20, 0, 1)
+    assert L.nbody_hermite_create(h, C.byref(hp), 100, C.byref(o2)) == -1
+    o3 = nb.HermiteOpts(1.0, 0.01, -1.0, 0.01, -20, -3, 0, 1)
+    assert L.nbody_hermite_create(h, C.byref(hp), 100, C.byref(o3)) == -1
+    o4 = nb.HermiteOpts(1.0, 0.01, 0.02, 0.01, -20, -3, 5, 1)
+    assert L.nbody_hermite_create(h, C.byref(hp), 100, C.byref(o4)) == -1
+    assert L.nbody_hermite_create(h, C.byref(hp), 100, C.byref(o)) == -4
+    assert L.nbody_hermite_step(None, None, None, None) == -1
+    assert L.nbody_destroy(None) == 0
+
+
+def test_create_rejects_bad_device():
+    import ctypes as C
+    L = nb.lib()
+    h = C.c_void_p(1)
+    assert L.nbody_create(C.byref(h), -2, None) == -1
+    assert not h.value
+    assert L.nbody_create(None, 0, None) == -1
+
+
+def test_block_level_matches_oracle_golden_cases():
+    with open(os.path.join(ROOT, "tests", "golden", "quantise_cases.json")) as f:
+        cases = json.load(f)["cases"]
+    for crit, dt_old, t_new, lmin, lmax, want, why in cases:
+        assert nb.block_level(float(crit), dt_old, t_new, lmin, lmax) == want, why
+
+
+def test_block_level_matches_oracle_random():
+    g = np.random.default_rng(0)
+    for _ in range(3000):
+        lmin = int(g.integers(-20, -5)); lmax = int(g.integers(lmin, 0))
+        crit = float(2.0 ** g.uniform(-24, 2)) * (1 if g.random() > 0.05 else -1)
+        dt_old = 0 if g.random() < 0.2 else int(1 << int(g.integers(lmin + 20, lmax + 21)))
+        t_new = int(g.integers(0, 1 << 22)) * max(dt_old, 1)
+        assert nb.block_level(crit, dt_old, t_new, lmin, lmax) == \
+            oracle.quantise_dt(crit, dt_old, t_new, lmin, lmax)
+    assert nb.block_level(0.1, 0, 0, -3, -20) == -1
