@@ -80,6 +80,13 @@ def lib():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_0707_0438_amd.build`")
+    # PyTorch ships its own HIP runtime (soname libamdhip64.so.7).  Loading it
+    # first makes libnbody bind to that same runtime instead of a second copy
+    # from the system ROCm, so tensors and streams are shared by one runtime.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = C.CDLL(LIB_PATH)
     P, I, I64, D = C.c_void_p, C.c_int, C.c_int64, C.c_double
     sig = {

@@ -144,3 +144,13 @@ def test_block_level_matches_oracle_random():
         assert nb.block_level(crit, dt_old, t_new, lmin, lmax) == \
             oracle.quantise_dt(crit, dt_old, t_new, lmin, lmax)
     assert nb.block_level(0.1, 0, 0, -3, -20) == -1
+
+
+def test_single_hip_runtime_in_process():
+    # libnbody must bind to the HIP runtime PyTorch already loaded, never a
+    # second copy (two runtimes in one process cannot share streams).
+    nb.lib()
+    import torch  # noqa: F401
+    maps = open("/proc/self/maps").read()
+    libs = set(re.findall(r"/\S*libamdhip64\S*", maps))
+    assert len(libs) == 1, libs
