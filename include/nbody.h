@@ -161,6 +161,73 @@ int nbody_force(nbody_ctx *ctx, hipStream_t stream, nbody_prec prec, double G, d
                 int64_t n_i, nbody_src I, const int32_t *i_self,
                 int64_t n_j, nbody_src J, nbody_out out);
 
+/* ---- adjoint of the force ------------------------------------------------- */
+
+/* Vector-Jacobian product of nbody_force (the derivative of the sums of
+ * Eq. 1 with Plummer softening, jerk and potential): for output cotangents
+ * ga (acceleration), gj (jerk), gp (potential) of the i-particles it returns
+ *   gxi, gvi = dL/dx_i, dL/dv_i   and   gxj, gvj, gmj = dL/dx_j, dL/dv_j, dL/dm_j
+ * of L = sum_i ga_i.a_i + gj_i.jerk_i + gp_i pot_i.  Per pair, with the
+ * notation of nbody_force and C = s^-5/2:
+ *   g_r = G m_j [s^-3/2 ga - P r - 3C (gj.r) u - 3C (r.u) gj],
+ *   P   = 3C (ga.r + gj.u - 5 (r.u)(gj.r)/s) - gp s^-3/2,
+ *   g_u = G m_j [s^-3/2 gj - 3C (gj.r) r],
+ * x_j gets +g_r, x_i gets -g_r (v likewise), and
+ *   dL/dm_j += G [s^-3/2 (ga.r + gj.u) - 3C (r.u)(gj.r) - gp s^-1/2].
+ * Self pairs (i_self) and, with eps = 0, pairs at zero separation are
+ * excluded as in nbody_force.
+ * Layout: ga, gj, gxi, gvi are single device pointers to float64 [3][n_i]
+ * (x row, y row, z row); gxj, gvj are [3][n_j]; gp is [n_i], gmj [n_j].
+ * gj and gp may be NULL (zero cotangents); any output may be NULL (not
+ * computed).  The i side and the j side are two passes (lane = i, then
+ * lane = j); both gather, no atomics, so results are run-to-run identical.
+ * Errors as nbody_force, plus NBODY_ERR_ARG for ga == NULL with n_i > 0. */
+int nbody_force_vjp(nbody_ctx *ctx, hipStream_t stream, nbody_prec prec, double G, double eps,
+                    int64_t n_i, nbody_src I, const int32_t *i_self, int64_t n_j, nbody_src J,
+                    const double *ga, const double *gj, const double *gp,
+                    double *gxi, double *gvi, double *gxj, double *gvj, double *gmj);
+
+/* The same adjoint for one self-gravitating set (every particle is both an
+ * i and a j, self excluded): returns the total gx = dL/dx, gv = dL/dv,
+ * gm = dL/dm of each particle in ONE fused pass in which a lane evaluates
+ * each pair once and applies both its own (i) and its partner's (j) half.
+ * Layout as nbody_force_vjp with n_i = n_j = n ([3][n] rows; gp, gm [n]). */
+int nbody_force_vjp_self(nbody_ctx *ctx, hipStream_t stream, nbody_prec prec, double G, double eps,
+                         int64_t n, nbody_src P, const double *ga, const double *gj, const double *gp,
+                         double *gx, double *gv, double *gm);
+
+/* ---- differentiable shared-step integration ---------------------------------- */
+
+/* Fourth-order Hermite integration of one self-gravitating set with one
+ * shared step dt for nsteps steps (Section 3, Makino & Aarseth 1992 scheme;
+ * every particle active every step, self excluded):
+ *   x_p = x + v dt + a dt^2/2 + j dt^3/6,  v_p = v + a dt + j dt^2/2,
+ *   (a1, j1) = force at (x_p, v_p),
+ *   a2 = (-6 (a - a1) - dt (4 j + 2 j1)) / dt^2,  a3 = (12 (a - a1) + 6 dt (j + j1)) / dt^3,
+ *   x = x_p + a2 dt^4/24 + a3 dt^5/120,  v = v_p + a2 dt^3/6 + a3 dt^4/24,  a = a1, j = j1,
+ * starting from (x0, v0) = P0 with a, j evaluated there.  x_out, v_out:
+ * device float64 [3][n].  ckpt: device buffer of nbody_shared_ckpt_bytes
+ * bytes (or NULL) that receives (x, v, a, j) before every ckpt_every-th
+ * step, for nbody_shared_adjoint. */
+int64_t nbody_shared_ckpt_bytes(int64_t n, int nsteps, int ckpt_every);
+int nbody_shared_run(nbody_ctx *ctx, hipStream_t stream, nbody_prec prec, double G, double eps,
+                     double dt, int nsteps, int64_t n, nbody_src P0, double *x_out, double *v_out,
+                     double *ckpt, int ckpt_every);
+
+/* Gradient of L = <gx_end, x(T)> + <gv_end, v(T)> of the run above with
+ * respect to x0, v0 and the masses.  Each checkpoint segment is recomputed
+ * forward (deterministically, so the predicted states match the first run
+ * bit for bit) and then differentiated step by step backwards:
+ * corrector adjoint (float64), the fused force adjoint of
+ * nbody_force_vjp_self with the acceleration and jerk cotangents, then the
+ * predictor adjoint (float64); finally the adjoint of the initial force
+ * evaluation.  gv_end may be NULL (zero).  gx0, gv0: [3][n]; gm: [n].
+ * Arguments must match the nbody_shared_run call that filled ckpt. */
+int nbody_shared_adjoint(nbody_ctx *ctx, hipStream_t stream, nbody_prec prec, double G, double eps,
+                         double dt, int nsteps, int64_t n, nbody_src P0, const double *ckpt,
+                         int ckpt_every, const double *gx_end, const double *gv_end,
+                         double *gx0, double *gv0, double *gm);
+
 /* ---- active-block selection (Section 3.1) ---------------------------------- */
 
 /* Block time steps: with integer times t[k] and steps dt[k] (device int64,

@@ -32,7 +32,8 @@ EXPORTS = [
     "nbody_hermite_set_state", "nbody_hermite_get_state", "nbody_hermite_step",
     "nbody_hermite_advance", "nbody_hermite_energy", "nbody_hermite_state_bytes",
     "nbody_hermite_save", "nbody_hermite_load", "nbody_block_level", "nbody_kernel_timing",
-    "nbody_kernel_time",
+    "nbody_kernel_time", "nbody_force_vjp", "nbody_force_vjp_self", "nbody_shared_ckpt_bytes",
+    "nbody_shared_run", "nbody_shared_adjoint",
 ]
 
 ERRORS = {0: "OK", -1: "NBODY_ERR_ARG", -2: "NBODY_ERR_NOMEM", -3: "NBODY_ERR_DEVICE",
@@ -114,6 +115,11 @@ def lib():
         "nbody_hermite_load": ([P, P, P], I),
         "nbody_block_level": ([D, I64, I64, I, I], I64),
         "nbody_kernel_timing": ([P, I], I),
+        "nbody_force_vjp": ([P, P, I, D, D, I64, Src, P, I64, Src, P, P, P, P, P, P, P, P], I),
+        "nbody_force_vjp_self": ([P, P, I, D, D, I64, Src, P, P, P, P, P, P], I),
+        "nbody_shared_ckpt_bytes": ([I64, I, I], I64),
+        "nbody_shared_run": ([P, P, I, D, D, D, I, I64, Src, P, P, P, I], I),
+        "nbody_shared_adjoint": ([P, P, I, D, D, D, I, I64, Src, P, I, P, P, P, P, P], I),
         "nbody_kernel_time": ([P, C.POINTER(D), C.POINTER(I64)], I),
     }
     for name, (args, res) in sig.items():
@@ -265,6 +271,91 @@ class Context:
         self._check(lib().nbody_force(self._h, _stream(stream), PREC[prec], float(G), float(eps),
                                       ni, I, sp, nj, J, O), "nbody_force")
         return acc, jerk, pot
+
+    def force_vjp(self, xi, vi, xj, vj, mj, eps, ga, gj=None, gp=None, G=1.0, prec="ds",
+                  i_self=None, want=("xi", "vi", "xj", "vj", "mj"), stream=None):
+        """Cotangents of x_i, v_i, x_j, v_j, m_j for output cotangents (ga, gj,
+        gp) of nbody_force; returns a dict with the requested keys."""
+        torch = _torch()
+        ni, nj = xi.shape[1], xj.shape[1]
+        I = _src(xi, vi, None, ni, "I")
+        J = _src(xj, vj, mj, nj, "J")
+        _rows(ga, ni, "ga")
+        if gj is not None:
+            _rows(gj, ni, "gj")
+        if gp is not None:
+            _vec(gp, ni, "gp")
+        dev = xi.device
+        out = {}
+        shapes = {"xi": (3, ni), "vi": (3, ni), "xj": (3, nj), "vj": (3, nj), "mj": (nj,)}
+        for k in want:
+            out[k] = torch.empty(shapes[k], dtype=torch.float64, device=dev)
+        ptr = lambda k: out[k].data_ptr() if k in out and out[k].numel() else None
+        sp = _vec(i_self, ni, "i_self", torch.int32) if i_self is not None else None
+        self._check(lib().nbody_force_vjp(
+            self._h, _stream(stream), PREC[prec], float(G), float(eps), ni, I, sp, nj, J,
+            ga.data_ptr() if ni else None, gj.data_ptr() if gj is not None and ni else None,
+            gp.data_ptr() if gp is not None and ni else None,
+            ptr("xi"), ptr("vi"), ptr("xj"), ptr("vj"), ptr("mj")), "nbody_force_vjp")
+        return out
+
+    def force_vjp_self(self, x, v, m, eps, ga, gj=None, gp=None, G=1.0, prec="ds", stream=None):
+        """(gx, gv, gm): total cotangents of one self-gravitating set (fused pass)."""
+        torch = _torch()
+        n = x.shape[1]
+        P = _src(x, v, m, n, "P")
+        _rows(ga, n, "ga")
+        if gj is not None:
+            _rows(gj, n, "gj")
+        if gp is not None:
+            _vec(gp, n, "gp")
+        gx = torch.empty((3, n), dtype=torch.float64, device=x.device)
+        gv = torch.empty((3, n), dtype=torch.float64, device=x.device)
+        gm = torch.empty((n,), dtype=torch.float64, device=x.device)
+        self._check(lib().nbody_force_vjp_self(
+            self._h, _stream(stream), PREC[prec], float(G), float(eps), n, P,
+            ga.data_ptr() if n else None, gj.data_ptr() if gj is not None and n else None,
+            gp.data_ptr() if gp is not None and n else None,
+            gx.data_ptr() if n else None, gv.data_ptr() if n else None,
+            gm.data_ptr() if n else None), "nbody_force_vjp_self")
+        return gx, gv, gm
+
+    def shared_run(self, x0, v0, m, eps, dt, nsteps, G=1.0, prec="ds", ckpt_every=8,
+                   checkpoints=True, stream=None):
+        """Shared-step Hermite run; returns (x_T, v_T, ckpt or None)."""
+        torch = _torch()
+        n = x0.shape[1]
+        P = _src(x0, v0, m, n, "P0")
+        xo = torch.empty((3, n), dtype=torch.float64, device=x0.device)
+        vo = torch.empty((3, n), dtype=torch.float64, device=x0.device)
+        ck = None
+        if checkpoints:
+            nbytes = lib().nbody_shared_ckpt_bytes(n, int(nsteps), int(ckpt_every))
+            ck = torch.empty((nbytes // 8,), dtype=torch.float64, device=x0.device)
+        self._check(lib().nbody_shared_run(self._h, _stream(stream), PREC[prec], float(G), float(eps),
+                                           float(dt), int(nsteps), n, P, xo.data_ptr(), vo.data_ptr(),
+                                           ck.data_ptr() if ck is not None else None, int(ckpt_every)),
+                    "nbody_shared_run")
+        return xo, vo, ck
+
+    def shared_adjoint(self, x0, v0, m, eps, dt, nsteps, ckpt, gx_end, gv_end=None, G=1.0, prec="ds",
+                       ckpt_every=8, stream=None):
+        """(gx0, gv0, gm) of L = <gx_end, x_T> + <gv_end, v_T>."""
+        torch = _torch()
+        n = x0.shape[1]
+        P = _src(x0, v0, m, n, "P0")
+        _rows(gx_end, n, "gx_end")
+        if gv_end is not None:
+            _rows(gv_end, n, "gv_end")
+        gx = torch.empty((3, n), dtype=torch.float64, device=x0.device)
+        gv = torch.empty((3, n), dtype=torch.float64, device=x0.device)
+        gm = torch.empty((n,), dtype=torch.float64, device=x0.device)
+        self._check(lib().nbody_shared_adjoint(
+            self._h, _stream(stream), PREC[prec], float(G), float(eps), float(dt), int(nsteps), n, P,
+            ckpt.data_ptr() if ckpt is not None else None, int(ckpt_every), gx_end.data_ptr(),
+            gv_end.data_ptr() if gv_end is not None else None, gx.data_ptr(), gv.data_ptr(),
+            gm.data_ptr()), "nbody_shared_adjoint")
+        return gx, gv, gm
 
     def autotune(self, xi, vi, xj, vj, mj, eps, G=1.0, prec="ds", reps=2, stream=None):
         torch = _torch()

@@ -32,7 +32,7 @@ struct DevBuf {
 struct nbody_ctx {
     int device = -1;          // -1: argument-checking context without a device
     std::string err;
-    DevBuf ipack, jpack, part, sel, scratch64;
+    DevBuf ipack, jpack, part, sel, scratch64, vrec_i, vrec_j, vpart, integ, hist;
     bool have_override[2] = {false, false};
     nbody_tile override_tile[2];
     nb::TuneCache tune;
@@ -313,7 +313,8 @@ int nbody_destroy(nbody_ctx* c) {
     if (c->device >= 0) {
         DeviceGuard g(c->device);
         for (hipEvent_t x : c->ev) (void)hipEventDestroy(x);
-        DevBuf* bufs[] = {&c->ipack, &c->jpack, &c->part, &c->sel, &c->scratch64};
+        DevBuf* bufs[] = {&c->ipack, &c->jpack, &c->part, &c->sel, &c->scratch64,
+                          &c->vrec_i, &c->vrec_j, &c->vpart, &c->integ, &c->hist};
         for (DevBuf* b : bufs)
             if (b->p) (void)hipFree(b->p);
     }
@@ -782,6 +783,333 @@ int nbody_hermite_load(nbody_hermite* h, hipStream_t st, const void* buf) {
     h->steps = hdr[2];
     h->sum_active = hdr[3];
     h->has_state = true;
+    return NBODY_OK;
+}
+
+// ---- adjoint ----------------------------------------------------------------
+
+static int vjp_split(int64_t nl, int64_t nt) {
+    const int64_t nblk = (nl + vjp_wg() - 1) / vjp_wg();
+    const int64_t target = 2048;
+    if (nblk <= 0 || nblk >= target / 2) return 1;
+    int64_t S = (target + nblk - 1) / nblk;
+    S = std::min<int64_t>(S, std::max<int64_t>(1, nt / (2 * (int64_t)vjp_tile())));
+    return (int)std::max<int64_t>(1, S);
+}
+
+static int pack_vjp(nbody_ctx* c, hipStream_t st, int prec, int64_t n, const nbody_src& s,
+                    const double* ga, const double* gj, const double* gp, int key_mode,
+                    const int32_t* iself, DevBuf& dst) {
+    int rc = dev_alloc(c, dst, sizeof(float4) * 5 * (size_t)std::max<int64_t>(n, 1));
+    if (rc) return rc;
+    VjpPackArgs p{};
+    p.n = (int)n;
+    p.prec = prec;
+    p.x = s.x; p.y = s.y; p.z = s.z;
+    p.vx = s.vx; p.vy = s.vy; p.vz = s.vz;
+    p.m = s.m;
+    p.ga = ga; p.gj = gj; p.gp = gp;
+    p.key_mode = key_mode;
+    p.iself = iself;
+    p.out = (float4*)dst.p;
+    hipError_t e = launch_vjp_pack(p, st);
+    if (e != hipSuccess) return hip_err(c, e, "adjoint pack launch");
+    return NBODY_OK;
+}
+
+static int run_vjp(nbody_ctx* c, hipStream_t st, int prec, bool own, bool partner, double G, double eps,
+                   int64_t nl, const float4* lrec, int64_t nt, const float4* trec, const double* ga,
+                   const double* gj, double* gx, double* gv, double* gm) {
+    if (nl == 0) return NBODY_OK;
+    const int Sreq = vjp_split(nl, nt);
+    int64_t jchunk = (nt + Sreq - 1) / Sreq;
+    jchunk = ((jchunk + vjp_tile() - 1) / vjp_tile()) * vjp_tile();
+    if (jchunk <= 0) jchunk = vjp_tile();
+    const int S = (int)std::max<int64_t>(1, (nt + jchunk - 1) / jchunk);
+    VjpArgs a{};
+    a.lrec = lrec;
+    a.nl = (int)nl;
+    a.trec = trec;
+    a.nt = (int)nt;
+    a.jchunk = (int)jchunk;
+    a.eps2 = (float)(eps * eps);
+    a.G = G;
+    a.own = own ? 1 : 0;
+    a.ga = ga;
+    a.gj = gj;
+    a.gx = gx;
+    a.gv = gv;
+    a.gm = gm;
+    if (S > 1) {
+        int rc = dev_alloc(c, c->vpart, sizeof(float2) * (size_t)vjp_acc() * (size_t)S * (size_t)nl);
+        if (rc) return rc;
+        a.part = (float2*)c->vpart.p;
+    }
+    hipError_t e = launch_vjp(prec, own, partner, S, a, st);
+    if (e != hipSuccess) return hip_err(c, e, "adjoint kernel launch");
+    return NBODY_OK;
+}
+
+static int check_rows3(nbody_ctx* c, const void* p, const char* name) {
+    if (p && !aligned8(p)) return set_err(c, NBODY_ERR_ARG, "%s is not 8-byte aligned", name);
+    return NBODY_OK;
+}
+
+int nbody_force_vjp(nbody_ctx* c, hipStream_t st, nbody_prec prec, double G, double eps, int64_t n_i,
+                    nbody_src I, const int32_t* i_self, int64_t n_j, nbody_src J, const double* ga,
+                    const double* gj, const double* gp, double* gxi, double* gvi, double* gxj, double* gvj,
+                    double* gmj) {
+    if (!c) return NBODY_ERR_ARG;
+    if (int rc = check_common(c, prec, G, eps)) return rc;
+    if (n_i < 0 || n_j < 0 || n_i > kMaxN || n_j > kMaxN)
+        return set_err(c, NBODY_ERR_ARG, "n_i and n_j must be in [0, 2^31-1]");
+    if (n_i > 0 && !ga) return set_err(c, NBODY_ERR_ARG, "ga must not be NULL");
+    const void* rows[8] = {ga, gj, gp, gxi, gvi, gxj, gvj, gmj};
+    const char* names[8] = {"ga", "gj", "gp", "gxi", "gvi", "gxj", "gvj", "gmj"};
+    for (int k = 0; k < 8; ++k)
+        if (int rc = check_rows3(c, rows[k], names[k])) return rc;
+    if (n_i > 0)
+        if (int rc = check_src(c, I, false, "I")) return rc;
+    if (n_j > 0)
+        if (int rc = check_src(c, J, true, "J")) return rc;
+    if (int rc = need_device(c)) return rc;
+    DeviceGuard g(c->device);
+    if (!g.ok) return set_err(c, NBODY_ERR_DEVICE, "hipSetDevice(%d) failed", c->device);
+    const int p = (int)prec;
+    const bool want_i = n_i > 0 && (gxi || gvi);
+    const bool want_j = n_j > 0 && (gxj || gvj || gmj);
+    if (n_i == 0 && want_j == false) return NBODY_OK;
+    int rc = NBODY_OK;
+    if (n_i > 0) rc = pack_vjp(c, st, p, n_i, I, ga, gj, gp, 1, i_self, c->vrec_i);
+    if (!rc && n_j > 0) rc = pack_vjp(c, st, p, n_j, J, nullptr, nullptr, nullptr, 0, nullptr, c->vrec_j);
+    if (rc) return rc;
+    if (want_i)
+        rc = run_vjp(c, st, p, true, false, G, eps, n_i, (const float4*)c->vrec_i.p, n_j,
+                     (const float4*)c->vrec_j.p, ga, gj, gxi, gvi, nullptr);
+    if (!rc && want_j)
+        rc = run_vjp(c, st, p, false, true, G, eps, n_j, (const float4*)c->vrec_j.p, n_i,
+                     (const float4*)c->vrec_i.p, nullptr, nullptr, gxj, gvj, gmj);
+    // (an empty partner set gives a launch with no tiles, which writes zeros)
+    return rc;
+}
+
+int nbody_force_vjp_self(nbody_ctx* c, hipStream_t st, nbody_prec prec, double G, double eps, int64_t n,
+                         nbody_src P, const double* ga, const double* gj, const double* gp, double* gx,
+                         double* gv, double* gm) {
+    if (!c) return NBODY_ERR_ARG;
+    if (int rc = check_common(c, prec, G, eps)) return rc;
+    if (n < 0 || n > kMaxN) return set_err(c, NBODY_ERR_ARG, "n must be in [0, 2^31-1]");
+    if (n > 0 && !ga) return set_err(c, NBODY_ERR_ARG, "ga must not be NULL");
+    const void* rows[6] = {ga, gj, gp, gx, gv, gm};
+    const char* names[6] = {"ga", "gj", "gp", "gx", "gv", "gm"};
+    for (int k = 0; k < 6; ++k)
+        if (int rc = check_rows3(c, rows[k], names[k])) return rc;
+    if (n > 0)
+        if (int rc = check_src(c, P, true, "P")) return rc;
+    if (int rc = need_device(c)) return rc;
+    if (n == 0 || !(gx || gv || gm)) return NBODY_OK;
+    DeviceGuard g(c->device);
+    if (!g.ok) return set_err(c, NBODY_ERR_DEVICE, "hipSetDevice(%d) failed", c->device);
+    const int p = (int)prec;
+    int rc = pack_vjp(c, st, p, n, P, ga, gj, gp, 0, nullptr, c->vrec_i);
+    if (rc) return rc;
+    return run_vjp(c, st, p, true, true, G, eps, n, (const float4*)c->vrec_i.p, n, (const float4*)c->vrec_i.p,
+                   ga, gj, gx, gv, gm);
+}
+
+// ---- shared-step run and its adjoint -------------------------------------------
+
+namespace {
+struct SharedWS {
+    double *x, *v, *a, *j, *f, *X, *V, *Aa, *Jj, *ga, *gj, *tx, *tv, *tm;
+};
+}  // namespace
+
+static int shared_ws(nbody_ctx* c, int64_t n, SharedWS* w) {
+    const size_t n3 = 3 * (size_t)n, nn = (size_t)n;
+    const size_t per = 12 * n3 + 8 * nn;   // x v a j X V Aa Jj ga gj tx tv (3n each), f (7n), tm (n)
+    int rc = dev_alloc(c, c->integ, sizeof(double) * per);
+    if (rc) return rc;
+    double* p = (double*)c->integ.p;
+    double** v3[] = {&w->x, &w->v, &w->a, &w->j, &w->X, &w->V, &w->Aa, &w->Jj, &w->ga, &w->gj, &w->tx, &w->tv};
+    for (double** q : v3) {
+        *q = p;
+        p += n3;
+    }
+    w->f = p;
+    p += 7 * nn;
+    w->tm = p;
+    return NBODY_OK;
+}
+
+static int copy_src3(nbody_ctx* c, hipStream_t st, int64_t n, const double* r0, const double* r1,
+                     const double* r2, double* dst) {
+    const size_t b = sizeof(double) * (size_t)n;
+    const double* rows[3] = {r0, r1, r2};
+    for (int k = 0; k < 3; ++k) {
+        hipError_t e = hipMemcpyAsync(dst + k * (size_t)n, rows[k], b, hipMemcpyDeviceToDevice, st);
+        if (e != hipSuccess) return hip_err(c, e, "state copy");
+    }
+    return NBODY_OK;
+}
+
+static nbody_src rows_src(const double* x, const double* v, const double* m, int64_t n) {
+    nbody_src s;
+    s.x = x; s.y = x + n; s.z = x + 2 * n;
+    s.vx = v; s.vy = v + n; s.vz = v + 2 * n;
+    s.m = m;
+    return s;
+}
+
+// a, j (and pot into f + 6n) of the set (x, v, m) with self excluded.
+static int shared_force(nbody_ctx* c, hipStream_t st, int prec, double G, double eps, int64_t n,
+                        const double* x, const double* v, const double* m, double* a3, double* j3,
+                        double* pot) {
+    int rc = pack_rows(c, st, prec, n, rows_src(x, v, m, n), true, c->jpack);
+    if (rc) return rc;
+    double* o[7] = {a3, a3 + n, a3 + 2 * n, j3, j3 + n, j3 + 2 * n, pot};
+    return run_force(c, st, prec, G, eps, n, (const float4*)c->jpack.p, nullptr, nullptr, 2, n,
+                     (const float4*)c->jpack.p, o, nullptr);
+}
+
+// One step from (w.x, w.v, w.a, w.j); the predicted state goes to xp, vp.
+static int shared_step(nbody_ctx* c, hipStream_t st, int prec, double G, double eps, double D, int64_t n,
+                       const double* m, SharedWS& w, double* xp, double* vp) {
+    hipError_t e = launch_shared_predict((int)n, D, w.x, w.v, w.a, w.j, xp, vp, st);
+    if (e != hipSuccess) return hip_err(c, e, "predict launch");
+    int rc = shared_force(c, st, prec, G, eps, n, xp, vp, m, w.f, w.f + 3 * n, w.f + 6 * n);
+    if (rc) return rc;
+    e = launch_shared_correct((int)n, D, xp, vp, w.x, w.v, w.a, w.j, w.f, w.f + 3 * n, st);
+    if (e != hipSuccess) return hip_err(c, e, "corrector launch");
+    return NBODY_OK;
+}
+
+static int check_shared(nbody_ctx* c, nbody_prec prec, double G, double eps, double dt, int nsteps, int64_t n,
+                        int every) {
+    if (int rc = check_common(c, prec, G, eps)) return rc;
+    if (!(dt > 0.0) || !isfinite(dt)) return set_err(c, NBODY_ERR_ARG, "dt must be positive and finite");
+    if (nsteps < 0) return set_err(c, NBODY_ERR_ARG, "nsteps must be >= 0");
+    if (n < 1 || n > kMaxN) return set_err(c, NBODY_ERR_ARG, "n must be in [1, 2^31-1]");
+    if (every < 1) return set_err(c, NBODY_ERR_ARG, "ckpt_every must be >= 1");
+    return NBODY_OK;
+}
+
+int64_t nbody_shared_ckpt_bytes(int64_t n, int nsteps, int every) {
+    if (n < 1 || nsteps < 0 || every < 1) return -1;
+    const int64_t nseg = (nsteps + every - 1) / every;
+    return std::max<int64_t>(nseg, 1) * 12 * n * (int64_t)sizeof(double);
+}
+
+int nbody_shared_run(nbody_ctx* c, hipStream_t st, nbody_prec prec, double G, double eps, double dt, int nsteps,
+                     int64_t n, nbody_src P0, double* x_out, double* v_out, double* ckpt, int every) {
+    if (!c) return NBODY_ERR_ARG;
+    if (int rc = check_shared(c, prec, G, eps, dt, nsteps, n, every)) return rc;
+    if (int rc = check_src(c, P0, true, "P0")) return rc;
+    if (!x_out || !v_out || !aligned8(x_out) || !aligned8(v_out) || (ckpt && !aligned8(ckpt)))
+        return set_err(c, NBODY_ERR_ARG, "x_out and v_out must be 8-byte aligned device pointers");
+    if (int rc = need_device(c)) return rc;
+    DeviceGuard g(c->device);
+    SharedWS w;
+    int rc = shared_ws(c, n, &w);
+    if (rc) return rc;
+    const int p = (int)prec;
+    rc = copy_src3(c, st, n, P0.x, P0.y, P0.z, w.x);
+    if (!rc) rc = copy_src3(c, st, n, P0.vx, P0.vy, P0.vz, w.v);
+    if (!rc) rc = shared_force(c, st, p, G, eps, n, w.x, w.v, P0.m, w.a, w.j, w.f + 6 * n);
+    if (rc) return rc;
+    const size_t n3 = 3 * (size_t)n;
+    // predicted states of a step land in the tx / tv scratch rows
+    for (int s = 0; s < nsteps; ++s) {
+        if (ckpt && s % every == 0) {
+            double* cp = ckpt + (size_t)(s / every) * 4 * n3;
+            const double* src[4] = {w.x, w.v, w.a, w.j};
+            for (int k = 0; k < 4; ++k) {
+                hipError_t e = hipMemcpyAsync(cp + k * n3, src[k], sizeof(double) * n3, hipMemcpyDeviceToDevice, st);
+                if (e != hipSuccess) return hip_err(c, e, "checkpoint copy");
+            }
+        }
+        rc = shared_step(c, st, p, G, eps, dt, n, P0.m, w, w.tx, w.tv);
+        if (rc) return rc;
+    }
+    hipError_t e = hipMemcpyAsync(x_out, w.x, sizeof(double) * n3, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(v_out, w.v, sizeof(double) * n3, hipMemcpyDeviceToDevice, st);
+    if (e != hipSuccess) return hip_err(c, e, "state copy out");
+    return NBODY_OK;
+}
+
+int nbody_shared_adjoint(nbody_ctx* c, hipStream_t st, nbody_prec prec, double G, double eps, double dt,
+                         int nsteps, int64_t n, nbody_src P0, const double* ckpt, int every, const double* gx_end,
+                         const double* gv_end, double* gx0, double* gv0, double* gm) {
+    if (!c) return NBODY_ERR_ARG;
+    if (int rc = check_shared(c, prec, G, eps, dt, nsteps, n, every)) return rc;
+    if (int rc = check_src(c, P0, true, "P0")) return rc;
+    if (nsteps > 0 && !ckpt) return set_err(c, NBODY_ERR_ARG, "ckpt must hold the forward checkpoints");
+    if (!gx_end || !gx0 || !gv0 || !gm) return set_err(c, NBODY_ERR_ARG, "NULL gradient pointer");
+    const void* al[6] = {ckpt, gx_end, gv_end, gx0, gv0, gm};
+    for (const void* q : al)
+        if (q && !aligned8(q)) return set_err(c, NBODY_ERR_ARG, "pointer not 8-byte aligned");
+    if (int rc = need_device(c)) return rc;
+    DeviceGuard g(c->device);
+    SharedWS w;
+    int rc = shared_ws(c, n, &w);
+    if (rc) return rc;
+    const int p = (int)prec;
+    const size_t n3 = 3 * (size_t)n;
+    const int every_eff = std::min(every, std::max(nsteps, 1));
+    rc = dev_alloc(c, c->hist, sizeof(double) * 2 * n3 * (size_t)every_eff);
+    if (rc) return rc;
+    double* hist = (double*)c->hist.p;
+    hipError_t e = hipMemcpyAsync(w.X, gx_end, sizeof(double) * n3, hipMemcpyDeviceToDevice, st);
+    if (e != hipSuccess) return hip_err(c, e, "cotangent copy");
+    if (gv_end) {
+        e = hipMemcpyAsync(w.V, gv_end, sizeof(double) * n3, hipMemcpyDeviceToDevice, st);
+    } else {
+        e = launch_fill_f64((int)n3, w.V, 0.0, st);
+    }
+    if (e == hipSuccess) e = launch_fill_f64((int)n3, w.Aa, 0.0, st);
+    if (e == hipSuccess) e = launch_fill_f64((int)n3, w.Jj, 0.0, st);
+    if (e == hipSuccess) e = launch_fill_f64((int)n, gm, 0.0, st);
+    if (e != hipSuccess) return hip_err(c, e, "adjoint clear");
+    const int nseg = (nsteps + every - 1) / every;
+    for (int seg = nseg - 1; seg >= 0; --seg) {
+        const int s0 = seg * every, s1 = std::min(nsteps, s0 + every);
+        const double* cp = ckpt + (size_t)seg * 4 * n3;
+        double* dst[4] = {w.x, w.v, w.a, w.j};
+        for (int k = 0; k < 4; ++k) {
+            e = hipMemcpyAsync(dst[k], cp + k * n3, sizeof(double) * n3, hipMemcpyDeviceToDevice, st);
+            if (e != hipSuccess) return hip_err(c, e, "checkpoint restore");
+        }
+        for (int s = s0; s < s1; ++s) {
+            double* xp = hist + (size_t)(s - s0) * 2 * n3;
+            rc = shared_step(c, st, p, G, eps, dt, n, P0.m, w, xp, xp + n3);
+            if (rc) return rc;
+        }
+        for (int s = s1 - 1; s >= s0; --s) {
+            const double* xp = hist + (size_t)(s - s0) * 2 * n3;
+            e = launch_adj_correct((int)n, dt, w.X, w.V, w.Aa, w.Jj, w.ga, w.gj, st);
+            if (e != hipSuccess) return hip_err(c, e, "corrector adjoint launch");
+            rc = pack_vjp(c, st, p, n, rows_src(xp, xp + n3, P0.m, n), w.ga, w.gj, nullptr, 0, nullptr, c->vrec_i);
+            if (!rc)
+                rc = run_vjp(c, st, p, true, true, G, eps, n, (const float4*)c->vrec_i.p, n,
+                             (const float4*)c->vrec_i.p, w.ga, w.gj, w.tx, w.tv, w.tm);
+            if (rc) return rc;
+            e = launch_axpy((int)n, gm, w.tm, st);
+            if (e == hipSuccess) e = launch_adj_predict((int)n, dt, w.X, w.V, w.Aa, w.Jj, w.tx, w.tv, st);
+            if (e != hipSuccess) return hip_err(c, e, "predictor adjoint launch");
+        }
+    }
+    // initial evaluation (a0, j0) = F(x0, v0, m)
+    rc = copy_src3(c, st, n, P0.x, P0.y, P0.z, w.x);
+    if (!rc) rc = copy_src3(c, st, n, P0.vx, P0.vy, P0.vz, w.v);
+    if (!rc) rc = pack_vjp(c, st, p, n, rows_src(w.x, w.v, P0.m, n), w.Aa, w.Jj, nullptr, 0, nullptr, c->vrec_i);
+    if (!rc)
+        rc = run_vjp(c, st, p, true, true, G, eps, n, (const float4*)c->vrec_i.p, n, (const float4*)c->vrec_i.p,
+                     w.Aa, w.Jj, w.tx, w.tv, w.tm);
+    if (rc) return rc;
+    e = launch_axpy((int)n, gm, w.tm, st);
+    if (e == hipSuccess) e = launch_sum2((int)n3, gx0, w.X, w.tx, st);
+    if (e == hipSuccess) e = launch_sum2((int)n3, gv0, w.V, w.tv, st);
+    if (e != hipSuccess) return hip_err(c, e, "adjoint final launch");
     return NBODY_OK;
 }
 

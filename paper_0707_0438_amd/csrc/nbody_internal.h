@@ -98,6 +98,48 @@ hipError_t launch_init_dt(const InitDtArgs& a, hipStream_t st);
 hipError_t launch_energy(int n, const double* vx, const double* vy, const double* vz,
                          const double* m, const double* pot, double* out2, hipStream_t st);
 
+// ---- adjoint (vjp.hip) ----
+struct VjpPackArgs {
+    int n, prec;
+    const double *x, *y, *z, *vx, *vy, *vz, *m;   // m may be NULL (0)
+    const double *ga, *gj, *gp;                    // [3][n], [3][n], [n]; NULL = 0
+    int key_mode;                                  // 0: key = index, 1: key = iself[k] (or -1)
+    const int32_t* iself;
+    float4* out;                                   // 5 float4 per particle
+};
+hipError_t launch_vjp_pack(const VjpPackArgs& a, hipStream_t st);
+
+struct VjpArgs {
+    const float4* lrec;   // lane particles
+    int nl;
+    const float4* trec;   // tile particles
+    int nt;
+    int jchunk;           // tile particles per split (multiple of the tile)
+    float eps2;
+    double G;
+    int own;              // lane cotangents enter (final combination reads ga, gj)
+    const double *ga, *gj;   // lane float64 cotangents [3][nl] (own only; NULL = 0)
+    double *gx, *gv, *gm;    // outputs [3][nl], [3][nl], [nl] (NULL: skip)
+    float2* part;            // split partials [S][9][nl] or NULL
+};
+hipError_t launch_vjp(int prec, bool own, bool partner, int S, const VjpArgs& a, hipStream_t st);
+int vjp_tile();
+int vjp_wg();
+int vjp_acc();
+
+// ---- shared-step integration and its adjoint (shared.hip); [3][n] rows ----
+hipError_t launch_shared_predict(int n, double D, const double* x, const double* v, const double* a,
+                                 const double* j, double* xp, double* vp, hipStream_t st);
+hipError_t launch_shared_correct(int n, double D, const double* xp, const double* vp, double* x, double* v,
+                                 double* a, double* j, const double* a1, const double* j1, hipStream_t st);
+hipError_t launch_adj_correct(int n, double D, const double* X, const double* V, double* Aa, double* Jj,
+                              double* ga, double* gj, hipStream_t st);
+hipError_t launch_adj_predict(int n, double D, double* X, double* V, double* Aa, double* Jj, const double* tx,
+                              const double* tv, hipStream_t st);
+hipError_t launch_axpy(int n, double* y, const double* x, hipStream_t st);
+hipError_t launch_sum2(int n, double* out, const double* a, const double* b, hipStream_t st);
+hipError_t launch_fill_f64(int n, double* y, double v, hipStream_t st);
+
 // p[0 .. n-1] = v (a kernel, so that graph capture records no memset node)
 hipError_t launch_fill_i64(int64_t* p, int n, int64_t v, hipStream_t st);
 

@@ -1,0 +1,134 @@
+"""GPU parity of the force adjoint (nbody_force_vjp, nbody_force_vjp_self)
+against the float64 oracle, plus identities that hold at any size."""
+import numpy as np
+import pytest
+
+import nbody_inputs as ics
+import oracle
+from gpu_util import dev, host, rel_err_stats
+
+pytestmark = pytest.mark.gpu
+
+# per-particle relative error bars (nearest-rank p99) of the gradients
+VJP_BARS = {"ds": 1e-5, "fp32": 1e-3}
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_0707_0438_amd as nb
+    c = nb.Context(0)
+    yield c
+    c.close()
+
+
+def cotangents(n, seed):
+    g = np.random.default_rng(seed)
+    return g.normal(size=(3, n)), g.normal(size=(3, n)), g.normal(size=n)
+
+
+def report(label, prec, pairs):
+    out = {}
+    for name, got, ref in pairs:
+        st = rel_err_stats(got, ref)
+        out[name] = st
+    print(label, prec, {k: f"p99={v['p99']:.2e} max={v['max']:.2e}" for k, v in out.items()}, flush=True)
+    return out
+
+
+@pytest.mark.parametrize("prec", ["ds", "fp32"])
+def test_vjp_self_against_oracle(ctx, prec):
+    p = ics.plummer(1500, 301)
+    eps = 1.0 / 256
+    ga, gj, gp = cotangents(p.n, 1)
+    gxi, gvi, gxj, gvj, gmj = oracle.force_vjp(p.pos, p.vel, p.pos, p.vel, p.mass, eps, ga, gj, gp,
+                                               iself=np.arange(p.n))
+    gx, gv, gm = ctx.force_vjp_self(dev(p.pos), dev(p.vel), dev(p.mass), eps, dev(ga), dev(gj),
+                                    dev(gp), prec=prec)
+    st = report("vjp_self n=1500", prec, [("gx", host(gx), gxi + gxj), ("gv", host(gv), gvi + gvj),
+                                          ("gm", host(gm), gmj)])
+    for k in st:
+        assert st[k]["p99"] <= VJP_BARS[prec], (k, st[k])
+
+
+@pytest.mark.parametrize("prec", ["ds", "fp32"])
+def test_vjp_general_subset_and_disjoint(ctx, prec):
+    import torch
+    p = ics.plummer(2100, 302)
+    eps = 0.01
+    sel = np.sort(np.random.default_rng(3).choice(p.n, 555, replace=False))
+    ga, gj, gp = cotangents(sel.size, 4)
+    ref = oracle.force_vjp(p.pos[:, sel], p.vel[:, sel], p.pos, p.vel, p.mass, eps, ga, gj, gp, iself=sel)
+    got = ctx.force_vjp(dev(p.pos[:, sel]), dev(p.vel[:, sel]), dev(p.pos), dev(p.vel), dev(p.mass), eps,
+                        dev(ga), dev(gj), dev(gp), prec=prec, i_self=dev(sel.astype(np.int32)))
+    torch.cuda.synchronize()
+    st = report("vjp subset", prec, [(k, host(got[k]), r) for k, r in zip(("xi", "vi", "xj", "vj", "mj"), ref)])
+    for k in st:
+        assert st[k]["p99"] <= VJP_BARS[prec], (k, st[k])
+    # disjoint sets, no jerk / potential cotangents
+    q = ics.plummer(301, 303)
+    ga2 = np.random.default_rng(5).normal(size=(3, q.n))
+    ref = oracle.force_vjp(q.pos, q.vel, p.pos, p.vel, p.mass, eps, ga2)
+    got = ctx.force_vjp(dev(q.pos), dev(q.vel), dev(p.pos), dev(p.vel), dev(p.mass), eps, dev(ga2), prec=prec)
+    st = report("vjp disjoint", prec, [(k, host(got[k]), r) for k, r in zip(("xi", "vi", "xj", "vj", "mj"), ref)])
+    for k in ("xi", "xj", "mj"):
+        assert st[k]["p99"] <= VJP_BARS[prec], (k, st[k])
+    # ga only: velocities do not enter a, so their cotangents vanish exactly
+    assert torch.count_nonzero(got["vi"]) == 0 and torch.count_nonzero(got["vj"]) == 0
+
+
+def test_vjp_fused_equals_two_pass(ctx):
+    import torch
+    p = ics.plummer(1200, 304)
+    ga, gj, gp = cotangents(p.n, 6)
+    X, V, M = dev(p.pos), dev(p.vel), dev(p.mass)
+    gx, gv, gm = ctx.force_vjp_self(X, V, M, 0.02, dev(ga), dev(gj), dev(gp))
+    two = ctx.force_vjp(X, V, X, V, M, 0.02, dev(ga), dev(gj), dev(gp),
+                        i_self=torch.arange(p.n, dtype=torch.int32, device="cuda"))
+    torch.cuda.synchronize()
+    st = report("fused vs two-pass", "ds", [("gx", host(gx), host(two["xi"] + two["xj"])),
+                                            ("gv", host(gv), host(two["vi"] + two["vj"])),
+                                            ("gm", host(gm), host(two["mj"]))])
+    for k in st:
+        assert st[k]["p99"] <= 1e-5
+
+
+def test_vjp_identities_at_plummer16k(ctx):
+    """N = 16384, eps = 1e-3 (the differentiation workload): translation and
+    Galilean invariance and mass homogeneity, which hold at any size."""
+    import torch
+    p = ics.workload("plummer16k_adjoint")
+    eps = 1e-3
+    ga, gj, gp = cotangents(p.n, 7)
+    X, V, M = dev(p.pos), dev(p.vel), dev(p.mass)
+    for prec in ("ds", "fp32"):
+        gx, gv, gm = ctx.force_vjp_self(X, V, M, eps, dev(ga), dev(gj), dev(gp), prec=prec)
+        a, j, pt = ctx.force(X, V, X, V, M, eps, prec=prec,
+                             i_self=torch.arange(p.n, dtype=torch.int32, device="cuda"))
+        torch.cuda.synchronize()
+        gx, gv, gm = host(gx), host(gv), host(gm)
+        L = (ga * host(a)).sum() + (gj * host(j)).sum() + (gp * host(pt)).sum()
+        sx = np.abs(gx.sum(axis=1)).max() / np.abs(gx).sum()
+        sv = np.abs(gv.sum(axis=1)).max() / np.abs(gv).sum()
+        hm = abs((p.mass * gm).sum() - L) / abs(L)
+        print(prec, "sum gx / sum|gx|", sx, "sum gv / sum|gv|", sv, "mass homogeneity", hm, flush=True)
+        bar = 1e-6 if prec == "ds" else 1e-4
+        assert sx < bar and sv < bar and hm < bar * 10
+
+
+def test_vjp_edge_sizes(ctx):
+    import torch
+    p = ics.plummer(3, 305)
+    ga = np.ones((3, 3))
+    gx, gv, gm = ctx.force_vjp_self(dev(p.pos), dev(p.vel), dev(p.mass), 0.1, dev(ga))
+    ref = oracle.force_vjp(p.pos, p.vel, p.pos, p.vel, p.mass, 0.1, ga, iself=np.arange(3))
+    np.testing.assert_allclose(host(gx), ref[0] + ref[2], rtol=1e-5, atol=1e-7)
+    one = ics.plummer(1, 306)
+    gx, gv, gm = ctx.force_vjp_self(dev(one.pos), dev(one.vel), dev(one.mass), 0.1, dev(np.ones((3, 1))))
+    torch.cuda.synchronize()
+    assert torch.count_nonzero(gx) == 0 and torch.count_nonzero(gm) == 0
+    # empty j set: i-side cotangents are zero
+    e = torch.empty((3, 0), dtype=torch.float64, device="cuda")
+    got = ctx.force_vjp(dev(p.pos), dev(p.vel), e, e, torch.empty((0,), dtype=torch.float64, device="cuda"),
+                        0.1, dev(ga), want=("xi", "vi"))
+    torch.cuda.synchronize()
+    assert torch.count_nonzero(got["xi"]) == 0
