@@ -94,6 +94,55 @@ def cpu_baseline(p, eps, budget_s):
                       f"all {n} (eps={eps}), {dt:.1f} s"}
 
 
+def adjoint_timing(nb, ctx, prec, reps=10):
+    """Adjoint/forward times at the differentiation workload (N = 16384,
+    eps = 1e-3): one force evaluation against the fused adjoint pass, and a
+    64-step shared Hermite run (dt = 1/128, checkpoints every 8) against its
+    checkpointed backward."""
+    import numpy as np
+    import torch
+    import nbody_inputs as ics
+    p = ics.workload("plummer16k_adjoint")
+    eps, dt, steps = 1e-3, 1.0 / 128, 64
+    X = torch.from_numpy(p.pos).to("cuda")
+    V = torch.from_numpy(p.vel).to("cuda")
+    M = torch.from_numpy(p.mass).to("cuda")
+    g = np.random.default_rng(1)
+    ga = torch.from_numpy(g.normal(size=(3, p.n))).to("cuda")
+    gj = torch.from_numpy(g.normal(size=(3, p.n))).to("cuda")
+    gp = torch.from_numpy(g.normal(size=p.n)).to("cuda")
+    S = torch.arange(p.n, dtype=torch.int32, device="cuda")
+
+    def timed(fn, k):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(k):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / k
+
+    t_f = timed(lambda: ctx.force(X, V, X, V, M, eps, prec=prec, i_self=S), reps)
+    t_b = timed(lambda: ctx.force_vjp_self(X, V, M, eps, ga, gj, gp, prec=prec), reps)
+    w = torch.from_numpy(ics.rng(ics.seed_for(3), 9).normal(size=(3, p.n))).to("cuda")
+    state = {}
+
+    def fwd():
+        state["ck"] = ctx.shared_run(X, V, M, eps, dt, steps, prec=prec, ckpt_every=8)[2]
+
+    t_run = timed(fwd, 2)
+    t_adj = timed(lambda: ctx.shared_adjoint(X, V, M, eps, dt, steps, state["ck"], w, prec=prec,
+                                             ckpt_every=8), 2)
+    return {"workload": "plummer16k_adjoint: N=16384, eps=1e-3; 64 shared Hermite steps of 1/128, "
+                        "checkpoints every 8",
+            "force_ms": round(t_f, 3), "vjp_ms": round(t_b, 3),
+            "adjoint_over_forward": round(t_b / t_f, 3),
+            "run_ms": round(t_run, 2), "run_backward_ms": round(t_adj, 2),
+            "backward_over_forward": round(t_adj / t_run, 3)}
+
+
 def copy_calibration(nbytes=1 << 30, reps=4):
     """A plain device-to-device copy of `nbytes` (read nbytes + write nbytes
     per launch), to scale the HBM counters of the force kernel."""
@@ -212,6 +261,8 @@ def main():
             "kernel_ms": round(o["kms"] / max(o["launches"], 1), 3),
             "pct_fp32_peak": round(100.0 * FLOPS_PER_INTERACTION * ov * 1e9 / (FP32_PEAK_TFLOPS * 1e12), 2),
         }
+    log("[bench] adjoint/forward timing")
+    line["adjoint"] = adjoint_timing(nb, ctx, args.prec)
     if args.cpu_budget > 0:
         log("[bench] cpu baseline (oracle)")
         line["cpu_baseline"] = cpu_baseline(p, eps, args.cpu_budget)

@@ -34,6 +34,21 @@ def rel_err_stats(got, ref):
     return {"p50": float(rank(0.5)), "p99": float(rank(0.99)), "max": float(e[-1])}
 
 
+def scaled_err_stats(got, ref):
+    """Per-element |got - ref| / rms(ref): for scalar gradients whose exact
+    value is a cancelling sum of random-sign terms (a relative error would
+    measure the accidental smallness of the sum, not the arithmetic)."""
+    got = np.asarray(got, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    rms = np.sqrt(np.mean(ref * ref)) if ref.size else 1.0
+    e = np.sort(np.abs(got - ref) / (rms if rms > 0 else 1.0))
+    n = e.size
+    if n == 0:
+        return {"p50": 0.0, "p99": 0.0, "max": 0.0}
+    rank = lambda q: e[max(0, int(np.ceil(q * n)) - 1)]
+    return {"p50": float(rank(0.5)), "p99": float(rank(0.99)), "max": float(e[-1])}
+
+
 # Accuracy bars (per-particle relative error, nearest-rank p99) against the
 # float64 oracle.  DS_COMP: the acceleration bar is the stated target
 # (1e-5); jerk and potential bars are the readings taken for them.  Plain

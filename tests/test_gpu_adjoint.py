@@ -7,7 +7,7 @@ import pytest
 
 import nbody_inputs as ics
 import oracle
-from gpu_util import dev, host, rel_err_stats
+from gpu_util import dev, host, rel_err_stats, scaled_err_stats
 
 pytestmark = pytest.mark.gpu
 
@@ -47,8 +47,8 @@ def test_shared_adjoint_matches_oracle(ctx, prec, every):
     _, _, ck = ctx.shared_run(X, V, M, eps, dt, steps, prec=prec, ckpt_every=every)
     gx, gv, gm = ctx.shared_adjoint(X, V, M, eps, dt, steps, ck, dev(w), prec=prec, ckpt_every=every)
     torch.cuda.synchronize()
-    st = {k: rel_err_stats(g, r) for k, g, r in (("gx0", host(gx), rx), ("gv0", host(gv), rv),
-                                                 ("gm", host(gm), rm))}
+    st = {"gx0": rel_err_stats(host(gx), rx), "gv0": rel_err_stats(host(gv), rv),
+          "gm": scaled_err_stats(host(gm), rm)}
     print(prec, every, {k: f"p99={v['p99']:.2e} max={v['max']:.2e}" for k, v in st.items()}, flush=True)
     bar = 1e-4 if prec == "ds" else 1e-2
     for k in st:
@@ -109,14 +109,14 @@ def test_autograd_functions(ctx):
     (w * xT).sum().backward()
     rx, rv, rm = oracle.hermite_shared_adjoint(p.pos, p.vel, p.mass, 1e-2, 1.0 / 64, 10, host(w))
     assert rel_err_stats(host(X.grad), rx)["p99"] < 1e-4
-    assert rel_err_stats(host(M.grad), rm)["p99"] < 1e-4
+    assert scaled_err_stats(host(M.grad), rm)["p99"] < 1e-4
     X.grad = None; V.grad = None; M.grad = None
     a, j, pt = NBodyForce.apply(ctx, X, V, M, 0.05)
     ga = np.random.default_rng(13).normal(size=(3, p.n))
     (dev(ga) * a).sum().backward()
     ref = oracle.force_vjp(p.pos, p.vel, p.pos, p.vel, p.mass, 0.05, ga, iself=np.arange(p.n))
     assert rel_err_stats(host(X.grad), ref[0] + ref[2])["p99"] < 1e-5
-    assert rel_err_stats(host(M.grad), ref[4])["p99"] < 1e-5
+    assert scaled_err_stats(host(M.grad), ref[4])["p99"] < 1e-5
 
 
 def test_plummer16k_gradient_identities(ctx):
