@@ -228,6 +228,48 @@ int nbody_shared_adjoint(nbody_ctx *ctx, hipStream_t stream, nbody_prec prec, do
                          int ckpt_every, const double *gx_end, const double *gv_end,
                          double *gx0, double *gv0, double *gm);
 
+/* ---- many independent clusters ------------------------------------------------- */
+
+/* Acceleration, jerk and potential (as nbody_force) of n_clusters
+ * independent clusters in ONE persistent launch.  Cluster c holds the
+ * particles [offsets[c], offsets[c+1]) of the concatenated rows P (device
+ * rows of length n_total); every particle of a cluster is both an i and a j
+ * (self excluded), there are no cross-cluster forces, and cluster c uses
+ * softening eps[c].  offsets (int64 [n_clusters+1]) and eps (float64
+ * [n_clusters]) are DEVICE arrays; ranges are clamped to [0, n_total], and
+ * particles outside every cluster get zero output.  A one-work-group plan
+ * kernel orders the clusters by size (largest first) and cuts them into
+ * (cluster, i-block) work items; the persistent kernel's work-groups take
+ * items from a device counter until none is left, each running the same
+ * tile loop as nbody_force.  With the same launch shape forced
+ * (nbody_set_tile, split 1) a cluster's rows equal nbody_force on that
+ * cluster bit for bit.  Kernels only (no host synchronisation); scratch
+ * grows on the first call, so capture into a graph after one call. */
+int nbody_force_batched(nbody_ctx *ctx, hipStream_t stream, nbody_prec prec, double G,
+                        int32_t n_clusters, const int64_t *offsets, const double *eps,
+                        int64_t n_total, nbody_src P, nbody_out out);
+
+/* nsteps shared Hermite steps of length dt for every cluster at once (the
+ * scheme of nbody_shared_run, forces from the batched kernel).  x, v, a, j:
+ * device float64 [3][n_total] state, updated in place; a and j must hold the
+ * forces at the starting state (e.g. from nbody_force_batched).  m: [n_total].
+ * use_graph = 1 captures the whole nsteps-step sequence (plan, then per step
+ * predict, pack, batched force, correct) into one hipGraph on a
+ * context-owned stream the first time a given argument set is seen and
+ * replays it afterwards, ordered after and before `stream` by events. */
+int nbody_batch_hermite(nbody_ctx *ctx, hipStream_t stream, nbody_prec prec, double G,
+                        int32_t n_clusters, const int64_t *offsets, const double *eps,
+                        int64_t n_total, double dt, int nsteps, double *x, double *v, double *a,
+                        double *j, const double *m, int use_graph);
+
+/* Autotuner of the batched launch: times every launch shape on the given
+ * clusters and keeps the fastest for this precision and (n_total,
+ * n_clusters) bucket.  As nbody_autotune. */
+int nbody_autotune_batched(nbody_ctx *ctx, hipStream_t stream, nbody_prec prec, double G,
+                           int32_t n_clusters, const int64_t *offsets, const double *eps,
+                           int64_t n_total, nbody_src P, nbody_out out, int reps,
+                           nbody_tile *best, double *best_ms);
+
 /* ---- active-block selection (Section 3.1) ---------------------------------- */
 
 /* Block time steps: with integer times t[k] and steps dt[k] (device int64,

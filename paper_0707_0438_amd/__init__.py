@@ -33,7 +33,8 @@ EXPORTS = [
     "nbody_hermite_advance", "nbody_hermite_energy", "nbody_hermite_state_bytes",
     "nbody_hermite_save", "nbody_hermite_load", "nbody_block_level", "nbody_kernel_timing",
     "nbody_kernel_time", "nbody_force_vjp", "nbody_force_vjp_self", "nbody_shared_ckpt_bytes",
-    "nbody_shared_run", "nbody_shared_adjoint",
+    "nbody_shared_run", "nbody_shared_adjoint", "nbody_force_batched", "nbody_batch_hermite",
+    "nbody_autotune_batched",
 ]
 
 ERRORS = {0: "OK", -1: "NBODY_ERR_ARG", -2: "NBODY_ERR_NOMEM", -3: "NBODY_ERR_DEVICE",
@@ -118,6 +119,10 @@ def lib():
         "nbody_force_vjp": ([P, P, I, D, D, I64, Src, P, I64, Src, P, P, P, P, P, P, P, P], I),
         "nbody_force_vjp_self": ([P, P, I, D, D, I64, Src, P, P, P, P, P, P], I),
         "nbody_shared_ckpt_bytes": ([I64, I, I], I64),
+        "nbody_force_batched": ([P, P, I, D, C.c_int32, P, P, I64, Src, Out], I),
+        "nbody_batch_hermite": ([P, P, I, D, C.c_int32, P, P, I64, D, I, P, P, P, P, P, I], I),
+        "nbody_autotune_batched": ([P, P, I, D, C.c_int32, P, P, I64, Src, Out, I, C.POINTER(Tile),
+                                    C.POINTER(D)], I),
         "nbody_shared_run": ([P, P, I, D, D, D, I, I64, Src, P, P, P, I], I),
         "nbody_shared_adjoint": ([P, P, I, D, D, D, I, I64, Src, P, I, P, P, P, P, P], I),
         "nbody_kernel_time": ([P, C.POINTER(D), C.POINTER(I64)], I),
@@ -356,6 +361,61 @@ class Context:
             gv_end.data_ptr() if gv_end is not None else None, gx.data_ptr(), gv.data_ptr(),
             gm.data_ptr()), "nbody_shared_adjoint")
         return gx, gv, gm
+
+    def force_batched(self, x, v, m, offsets, eps, G=1.0, prec="ds", out=None, stream=None):
+        """Forces of independent clusters (concatenated rows); offsets int64
+        (C+1,) and eps float64 (C,) are GPU tensors.  Returns (acc, jerk, pot)."""
+        torch = _torch()
+        n = x.shape[1]
+        C_ = int(eps.shape[0])
+        P = _src(x, v, m, n, "P")
+        if out is None:
+            acc = torch.empty((3, n), dtype=torch.float64, device=x.device)
+            jerk = torch.empty((3, n), dtype=torch.float64, device=x.device)
+            pot = torch.empty((n,), dtype=torch.float64, device=x.device)
+        else:
+            acc, jerk, pot = out
+        a, j = _rows(acc, n, "acc"), _rows(jerk, n, "jerk")
+        O = Out(a[0], a[1], a[2], j[0], j[1], j[2], _vec(pot, n, "pot"))
+        op = _vec(offsets, C_ + 1, "offsets", torch.int64)
+        ep = _vec(eps, C_, "eps") if C_ else None
+        self._check(lib().nbody_force_batched(self._h, _stream(stream), PREC[prec], float(G), C_, op, ep,
+                                              n, P, O), "nbody_force_batched")
+        return acc, jerk, pot
+
+    def batch_hermite(self, x, v, a, j, m, offsets, eps, dt, nsteps, G=1.0, prec="ds", use_graph=True,
+                      stream=None):
+        """Advance every cluster nsteps shared Hermite steps in place."""
+        torch = _torch()
+        n = x.shape[1]
+        C_ = int(eps.shape[0])
+        for t, nm in ((x, "x"), (v, "v"), (a, "a"), (j, "j")):
+            _rows(t, n, nm)
+        _vec(m, n, "m")
+        op = _vec(offsets, C_ + 1, "offsets", torch.int64)
+        ep = _vec(eps, C_, "eps") if C_ else None
+        self._check(lib().nbody_batch_hermite(self._h, _stream(stream), PREC[prec], float(G), C_, op, ep, n,
+                                              float(dt), int(nsteps), x.data_ptr(), v.data_ptr(), a.data_ptr(),
+                                              j.data_ptr(), m.data_ptr(), 1 if use_graph else 0),
+                    "nbody_batch_hermite")
+
+    def autotune_batched(self, x, v, m, offsets, eps, G=1.0, prec="ds", reps=2, stream=None):
+        torch = _torch()
+        n = x.shape[1]
+        C_ = int(eps.shape[0])
+        P = _src(x, v, m, n, "P")
+        acc = torch.empty((3, n), dtype=torch.float64, device=x.device)
+        jerk = torch.empty((3, n), dtype=torch.float64, device=x.device)
+        pot = torch.empty((n,), dtype=torch.float64, device=x.device)
+        a, j = _rows(acc, n, "acc"), _rows(jerk, n, "jerk")
+        O = Out(a[0], a[1], a[2], j[0], j[1], j[2], _vec(pot, n, "pot"))
+        t = Tile()
+        ms = C.c_double()
+        self._check(lib().nbody_autotune_batched(self._h, _stream(stream), PREC[prec], float(G), C_,
+                                                 _vec(offsets, C_ + 1, "offsets", torch.int64),
+                                                 _vec(eps, C_, "eps"), n, P, O, int(reps), C.byref(t),
+                                                 C.byref(ms)), "nbody_autotune_batched")
+        return t.as_dict(), ms.value
 
     def autotune(self, xi, vi, xj, vj, mj, eps, G=1.0, prec="ds", reps=2, stream=None):
         torch = _torch()

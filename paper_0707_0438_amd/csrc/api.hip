@@ -32,7 +32,13 @@ struct DevBuf {
 struct nbody_ctx {
     int device = -1;          // -1: argument-checking context without a device
     std::string err;
-    DevBuf ipack, jpack, part, sel, scratch64, vrec_i, vrec_j, vpart, integ, hist;
+    DevBuf ipack, jpack, part, sel, scratch64, vrec_i, vrec_j, vpart, integ, hist, bplan, bstate;
+    // batched Hermite graph (captured on a context-owned stream)
+    hipStream_t gstream = nullptr;
+    hipEvent_t gev[2] = {nullptr, nullptr};
+    hipGraphExec_t gexec = nullptr;
+    hipGraph_t graph = nullptr;
+    std::vector<uint64_t> gkey;
     bool have_override[2] = {false, false};
     nbody_tile override_tile[2];
     nb::TuneCache tune;
@@ -313,8 +319,14 @@ int nbody_destroy(nbody_ctx* c) {
     if (c->device >= 0) {
         DeviceGuard g(c->device);
         for (hipEvent_t x : c->ev) (void)hipEventDestroy(x);
+        if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+        if (c->graph) (void)hipGraphDestroy(c->graph);
+        for (hipEvent_t x : c->gev)
+            if (x) (void)hipEventDestroy(x);
+        if (c->gstream) (void)hipStreamDestroy(c->gstream);
         DevBuf* bufs[] = {&c->ipack, &c->jpack, &c->part, &c->sel, &c->scratch64,
-                          &c->vrec_i, &c->vrec_j, &c->vpart, &c->integ, &c->hist};
+                          &c->vrec_i, &c->vrec_j, &c->vpart, &c->integ, &c->hist, &c->bplan,
+                          &c->bstate};
         for (DevBuf* b : bufs)
             if (b->p) (void)hipFree(b->p);
     }
@@ -1110,6 +1122,311 @@ int nbody_shared_adjoint(nbody_ctx* c, hipStream_t st, nbody_prec prec, double G
     if (e == hipSuccess) e = launch_sum2((int)n3, gx0, w.X, w.tx, st);
     if (e == hipSuccess) e = launch_sum2((int)n3, gv0, w.V, w.tv, st);
     if (e != hipSuccess) return hip_err(c, e, "adjoint final launch");
+    return NBODY_OK;
+}
+
+// ---- batched clusters -----------------------------------------------------------
+
+static nbody_tile batched_tile(nbody_ctx* c, int prec, int64_t n_total, int32_t n_clusters) {
+    nbody_tile t;
+    if (c->have_override[prec]) {
+        t = c->override_tile[prec];
+    } else if (!c->tune.lookup(prec + 2, n_total, n_clusters, &t)) {
+        t.tile_j = 64;
+        t.ipt = 1;
+        t.wg = 128;
+        t.split = 1;
+    }
+    t.split = 1;
+    return t;
+}
+
+namespace {
+struct BatchWS {
+    int *cbeg, *cend, *order, *start, *n_items, *counters;
+    int2* items;
+    int64_t cap;
+};
+}  // namespace
+
+static int batch_ws(nbody_ctx* c, int32_t C, int64_t n_total, int nsteps, BatchWS* w) {
+    const int64_t cap = n_total / 64 + (int64_t)C + 1;
+    const size_t ints = 4 * (size_t)std::max(C, 1) + 1 + (size_t)std::max(nsteps, 1);
+    const size_t bytes = sizeof(int2) * (size_t)cap + sizeof(int) * ints + 256;
+    int rc = dev_alloc(c, c->bplan, bytes);
+    if (rc) return rc;
+    int2* it = (int2*)c->bplan.p;
+    int* p = (int*)(it + cap);
+    const size_t Cn = (size_t)std::max(C, 1);
+    w->items = it;
+    w->cap = cap;
+    w->cbeg = p;
+    w->cend = p + Cn;
+    w->order = p + 2 * Cn;
+    w->start = p + 3 * Cn;
+    w->n_items = p + 4 * Cn;
+    w->counters = p + 4 * Cn + 1;
+    return NBODY_OK;
+}
+
+static int batch_plan(nbody_ctx* c, hipStream_t st, int32_t C, const int64_t* offsets, int64_t n_total,
+                      const nbody_tile& t, BatchWS& w) {
+    PlanArgs p{};
+    p.n_clusters = C;
+    p.offsets = offsets;
+    p.n_total = (int)n_total;
+    p.per = t.wg * t.ipt;
+    p.cap = w.cap;
+    p.cbeg = w.cbeg;
+    p.cend = w.cend;
+    p.order = w.order;
+    p.start = w.start;
+    p.n_items = w.n_items;
+    p.items = w.items;
+    hipError_t e = launch_batch_plan(p, st);
+    if (e != hipSuccess) return hip_err(c, e, "batch plan launch");
+    return NBODY_OK;
+}
+
+static int batch_force(nbody_ctx* c, hipStream_t st, int prec, double G, const nbody_tile& t, int64_t n_total,
+                       const double* eps, const BatchWS& w, int* counter, double* const out[7]) {
+    ForceArgs a{};
+    a.ipack = (const float4*)c->jpack.p;
+    a.iidx = nullptr;
+    a.ni = (int)n_total;
+    a.jpack = (const float4*)c->jpack.p;
+    a.nj = (int)n_total;
+    a.jchunk = (int)n_total;
+    a.eps2 = 0.f;
+    a.partial = 0;
+    a.G = G;
+    a.iself = nullptr;
+    a.self_mode = 2;
+    for (int q = 0; q < 7; ++q) a.out[q] = out[q];
+    BatchArgs b{};
+    b.items = w.items;
+    b.n_items = w.n_items;
+    b.counter = counter;
+    b.cbeg = w.cbeg;
+    b.cend = w.cend;
+    b.eps = eps;
+    const int per = t.wg * t.ipt;
+    const int64_t bound = n_total / per + 1 + (int64_t)(w.cap - n_total / 64 - 1);   // <= items
+    const int resident = 1024 * (256 / t.wg);
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(bound, resident));
+    hipError_t e = launch_fill_i32(counter, 1, 0, st);
+    if (e == hipSuccess) e = launch_force_batched(prec, t.ipt, t.tile_j, t.wg, grid, a, b, st);
+    if (e != hipSuccess) return hip_err(c, e, "batched force launch");
+    return NBODY_OK;
+}
+
+static int check_batched(nbody_ctx* c, nbody_prec prec, double G, int32_t C, const int64_t* offsets,
+                         const double* eps, int64_t n_total) {
+    if (prec != NBODY_PREC_FP32 && prec != NBODY_PREC_DS_COMP)
+        return set_err(c, NBODY_ERR_ARG, "unknown precision %d", (int)prec);
+    if (!isfinite(G)) return set_err(c, NBODY_ERR_ARG, "G must be finite");
+    if (C < 0 || C > (1 << 20)) return set_err(c, NBODY_ERR_ARG, "n_clusters must be in [0, 2^20]");
+    if (n_total < 0 || n_total > kMaxN) return set_err(c, NBODY_ERR_ARG, "n_total must be in [0, 2^31-1]");
+    if (C > 0 && (!offsets || !eps)) return set_err(c, NBODY_ERR_ARG, "offsets and eps must not be NULL");
+    if (!aligned8(offsets) || !aligned8(eps)) return set_err(c, NBODY_ERR_ARG, "offsets/eps not 8-byte aligned");
+    return NBODY_OK;
+}
+
+int nbody_force_batched(nbody_ctx* c, hipStream_t st, nbody_prec prec, double G, int32_t n_clusters,
+                        const int64_t* offsets, const double* eps, int64_t n_total, nbody_src P, nbody_out out) {
+    if (!c) return NBODY_ERR_ARG;
+    if (int rc = check_batched(c, prec, G, n_clusters, offsets, eps, n_total)) return rc;
+    if (n_total > 0) {
+        if (int rc = check_src(c, P, true, "P")) return rc;
+        if (int rc = check_out(c, out)) return rc;
+    }
+    if (int rc = need_device(c)) return rc;
+    if (n_total == 0) return NBODY_OK;
+    DeviceGuard g(c->device);
+    const int p = (int)prec;
+    const nbody_tile t = batched_tile(c, p, n_total, n_clusters);
+    BatchWS w;
+    int rc = batch_ws(c, n_clusters, n_total, 1, &w);
+    if (!rc) rc = dev_alloc(c, c->jpack, sizeof(float4) * rec_words(p) * (size_t)n_total);
+    if (rc) return rc;
+    // zero output for particles outside every cluster
+    double* o[7] = {out.ax, out.ay, out.az, out.jx, out.jy, out.jz, out.pot};
+    for (int q = 0; q < 7; ++q) {
+        hipError_t e = launch_fill_f64((int)n_total, o[q], 0.0, st);
+        if (e != hipSuccess) return hip_err(c, e, "output clear");
+    }
+    rc = pack_rows(c, st, p, n_total, P, true, c->jpack);
+    if (!rc) rc = batch_plan(c, st, n_clusters, offsets, n_total, t, w);
+    if (!rc && n_clusters > 0) rc = batch_force(c, st, p, G, t, n_total, eps, w, w.counters, o);
+    return rc;
+}
+
+// the step sequence of nbody_batch_hermite (kernels only: capturable)
+static int batch_hermite_enqueue(nbody_ctx* c, hipStream_t st, int p, double G, int32_t C, const int64_t* offsets,
+                                 const double* eps, int64_t n, double dt, int nsteps, double* x, double* v,
+                                 double* a3, double* j3, const double* m, const nbody_tile& t, BatchWS& w) {
+    const size_t n3 = 3 * (size_t)n;
+    double* xp = (double*)c->bstate.p;
+    double* vp = xp + n3;
+    double* f = vp + n3;
+    double* o[7] = {f, f + n, f + 2 * n, f + 3 * n, f + 4 * n, f + 5 * n, f + 6 * n};
+    int rc = batch_plan(c, st, C, offsets, n, t, w);
+    if (rc) return rc;
+    for (int s = 0; s < nsteps; ++s) {
+        hipError_t e = launch_shared_predict((int)n, dt, x, v, a3, j3, xp, vp, st);
+        if (e != hipSuccess) return hip_err(c, e, "predict launch");
+        PackArgs pa{};
+        pa.n = (int)n;
+        pa.prec = p;
+        pa.x = xp; pa.y = xp + n; pa.z = xp + 2 * n;
+        pa.vx = vp; pa.vy = vp + n; pa.vz = vp + 2 * n;
+        pa.m = m;
+        pa.out = (float4*)c->jpack.p;
+        e = launch_pack(pa, st);
+        if (e != hipSuccess) return hip_err(c, e, "pack launch");
+        rc = batch_force(c, st, p, G, t, n, eps, w, w.counters + s, o);
+        if (rc) return rc;
+        e = launch_shared_correct((int)n, dt, xp, vp, x, v, a3, j3, f, f + 3 * n, st);
+        if (e != hipSuccess) return hip_err(c, e, "corrector launch");
+    }
+    return NBODY_OK;
+}
+
+int nbody_batch_hermite(nbody_ctx* c, hipStream_t st, nbody_prec prec, double G, int32_t n_clusters,
+                        const int64_t* offsets, const double* eps, int64_t n_total, double dt, int nsteps, double* x,
+                        double* v, double* a3, double* j3, const double* m, int use_graph) {
+    if (!c) return NBODY_ERR_ARG;
+    if (int rc = check_batched(c, prec, G, n_clusters, offsets, eps, n_total)) return rc;
+    if (!(dt > 0.0) || !isfinite(dt)) return set_err(c, NBODY_ERR_ARG, "dt must be positive and finite");
+    if (nsteps < 0 || nsteps > 1000000) return set_err(c, NBODY_ERR_ARG, "nsteps must be in [0, 10^6]");
+    if (use_graph != 0 && use_graph != 1) return set_err(c, NBODY_ERR_ARG, "use_graph must be 0 or 1");
+    const void* ptrs[5] = {x, v, a3, j3, m};
+    for (const void* q : ptrs)
+        if (n_total > 0 && (!q || !aligned8(q))) return set_err(c, NBODY_ERR_ARG, "state rows must be aligned, non-NULL");
+    if (int rc = need_device(c)) return rc;
+    if (n_total == 0 || nsteps == 0 || n_clusters == 0) return NBODY_OK;
+    DeviceGuard g(c->device);
+    const int p = (int)prec;
+    const nbody_tile t = batched_tile(c, p, n_total, n_clusters);
+    BatchWS w;
+    int rc = batch_ws(c, n_clusters, n_total, nsteps, &w);
+    if (!rc) rc = dev_alloc(c, c->jpack, sizeof(float4) * rec_words(p) * (size_t)n_total);
+    if (!rc) rc = dev_alloc(c, c->bstate, sizeof(double) * 13 * (size_t)n_total);
+    if (rc) return rc;
+    if (!use_graph)
+        return batch_hermite_enqueue(c, st, p, G, n_clusters, offsets, eps, n_total, dt, nsteps, x, v, a3, j3, m, t, w);
+    // graph: capture once per argument signature, replay afterwards
+    uint64_t dtb;
+    memcpy(&dtb, &dt, sizeof dtb);
+    uint64_t Gb;
+    memcpy(&Gb, &G, sizeof Gb);
+    std::vector<uint64_t> key = {(uint64_t)p, Gb, (uint64_t)n_clusters, (uintptr_t)offsets, (uintptr_t)eps,
+                                 (uint64_t)n_total, dtb, (uint64_t)nsteps, (uintptr_t)x, (uintptr_t)v,
+                                 (uintptr_t)a3, (uintptr_t)j3, (uintptr_t)m, (uint64_t)t.tile_j,
+                                 (uint64_t)t.ipt, (uint64_t)t.wg, (uintptr_t)c->jpack.p, (uintptr_t)c->bplan.p,
+                                 (uintptr_t)c->bstate.p};
+    hipError_t e = hipSuccess;
+    if (!c->gstream) {
+        e = hipStreamCreateWithFlags(&c->gstream, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&c->gev[0], hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&c->gev[1], hipEventDisableTiming);
+        if (e != hipSuccess) return hip_err(c, e, "graph stream setup");
+    }
+    if (!c->gexec || c->gkey != key) {
+        if (c->gexec) {
+            (void)hipGraphExecDestroy(c->gexec);
+            c->gexec = nullptr;
+        }
+        if (c->graph) {
+            (void)hipGraphDestroy(c->graph);
+            c->graph = nullptr;
+        }
+        e = hipStreamBeginCapture(c->gstream, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return hip_err(c, e, "begin capture");
+        rc = batch_hermite_enqueue(c, c->gstream, p, G, n_clusters, offsets, eps, n_total, dt, nsteps, x, v, a3, j3,
+                                   m, t, w);
+        hipGraph_t gr = nullptr;
+        hipError_t e2 = hipStreamEndCapture(c->gstream, &gr);
+        if (rc) {
+            if (gr) (void)hipGraphDestroy(gr);
+            return rc;
+        }
+        if (e2 != hipSuccess) return hip_err(c, e2, "end capture");
+        e = hipGraphInstantiate(&c->gexec, gr, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            (void)hipGraphDestroy(gr);
+            return hip_err(c, e, "graph instantiate");
+        }
+        c->graph = gr;
+        c->gkey = key;
+    }
+    e = hipEventRecord(c->gev[0], st);
+    if (e == hipSuccess) e = hipStreamWaitEvent(c->gstream, c->gev[0], 0);
+    if (e == hipSuccess) e = hipGraphLaunch(c->gexec, c->gstream);
+    if (e == hipSuccess) e = hipEventRecord(c->gev[1], c->gstream);
+    if (e == hipSuccess) e = hipStreamWaitEvent(st, c->gev[1], 0);
+    if (e != hipSuccess) return hip_err(c, e, "graph launch");
+    return NBODY_OK;
+}
+
+int nbody_autotune_batched(nbody_ctx* c, hipStream_t st, nbody_prec prec, double G, int32_t n_clusters,
+                           const int64_t* offsets, const double* eps, int64_t n_total, nbody_src P, nbody_out out,
+                           int reps, nbody_tile* best, double* best_ms) {
+    if (!c) return NBODY_ERR_ARG;
+    if (reps < 1 || reps > 100) return set_err(c, NBODY_ERR_ARG, "reps must be in [1, 100]");
+    if (n_total <= 0 || n_clusters <= 0) return set_err(c, NBODY_ERR_ARG, "need clusters and particles");
+    if (int rc = check_batched(c, prec, G, n_clusters, offsets, eps, n_total)) return rc;
+    if (int rc = check_src(c, P, true, "P")) return rc;
+    if (int rc = check_out(c, out)) return rc;
+    if (int rc = need_device(c)) return rc;
+    DeviceGuard g(c->device);
+    const int p = (int)prec;
+    const bool had = c->have_override[p];
+    const nbody_tile saved = c->override_tile[p];
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return set_err(c, NBODY_ERR_DEVICE, "event create");
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return set_err(c, NBODY_ERR_DEVICE, "event create");
+    }
+    const int tjs[3] = {64, 128, 256}, ipts[3] = {1, 2, 4}, wgs[2] = {128, 256};
+    nbody_tile bt{};
+    double bms = 1e300;
+    int rc = NBODY_OK;
+    for (int a = 0; a < 3 && !rc; ++a)
+        for (int b = 0; b < 3 && !rc; ++b)
+            for (int wi = 0; wi < 2 && !rc; ++wi) {
+                nbody_tile t{tjs[a], ipts[b], wgs[wi], 1};
+                c->override_tile[p] = t;
+                c->have_override[p] = true;
+                rc = nbody_force_batched(c, st, prec, G, n_clusters, offsets, eps, n_total, P, out);
+                if (rc) break;
+                hipError_t e = hipEventRecord(e0, st);
+                for (int r = 0; r < reps && e == hipSuccess && !rc; ++r)
+                    rc = nbody_force_batched(c, st, prec, G, n_clusters, offsets, eps, n_total, P, out);
+                if (rc) break;
+                if (e == hipSuccess) e = hipEventRecord(e1, st);
+                if (e == hipSuccess) e = hipEventSynchronize(e1);
+                float ms = 0.f;
+                if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+                if (e != hipSuccess) {
+                    rc = hip_err(c, e, "autotune timing");
+                    break;
+                }
+                if (ms / reps < bms) {
+                    bms = ms / reps;
+                    bt = t;
+                }
+            }
+    c->have_override[p] = had;
+    c->override_tile[p] = saved;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    c->tune.store(p + 2, n_total, n_clusters, bt, bms);
+    if (!c->tune.save()) return set_err(c, NBODY_ERR_ARG, "cannot write tune cache %s", c->tune.path().c_str());
+    if (best) *best = bt;
+    if (best_ms) *best_ms = bms;
     return NBODY_OK;
 }
 

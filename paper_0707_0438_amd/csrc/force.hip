@@ -44,17 +44,17 @@ __device__ __forceinline__ void two_sum_fold(float& hi, float& lo, float p) {
     lo += e;
 }
 
+// One work-group's share: i slots ibase + k*WG + tid (k < IPT) below iend,
+// against j in [jb, je).  Results go to the float64 outputs (with the
+// self-potential removal) or to split partial slot `split`.
 template <int PREC, int IPT, int TJ, int WG, bool EPS0>
-__global__ __launch_bounds__(WG) void force_kernel(ForceArgs a) {
+__device__ __forceinline__ void force_block(const ForceArgs& a, float4 (*sh)[TJ * Rec<PREC>::R], int ibase,
+                                            int iend, int jb, int je, float eps2, int split) {
     constexpr int R = Rec<PREC>::R;
     constexpr int NE = TJ * R;                  // float4 per tile
     constexpr int NLD = (NE + WG - 1) / WG;     // staging loads per lane
-    __shared__ float4 sh[2][NE];
 
     const int tid = threadIdx.x;
-    const int ibase = blockIdx.x * (WG * IPT);
-    const int jb = blockIdx.y * a.jchunk;
-    const int je = min(a.nj, jb + a.jchunk);
     const int ntiles = je > jb ? (je - jb + TJ - 1) / TJ : 0;
 
     // i-particles of this lane
@@ -64,7 +64,7 @@ __global__ __launch_bounds__(WG) void force_kernel(ForceArgs a) {
     for (int k = 0; k < IPT; ++k) {
         const int ii = ibase + k * WG + tid;
         float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f), r1 = r0, r2 = r0;
-        if (ii < a.ni) {
+        if (ii < iend) {
             const int src = a.iidx ? a.iidx[ii] : ii;
             r0 = a.ipack[(size_t)src * R + 0];
             r1 = a.ipack[(size_t)src * R + 1];
@@ -107,7 +107,6 @@ __global__ __launch_bounds__(WG) void force_kernel(ForceArgs a) {
         }
     };
 
-    const float eps2 = a.eps2;
     if (ntiles > 0) {
         load_tile(0);
         store_tile(0);
@@ -171,7 +170,7 @@ __global__ __launch_bounds__(WG) void force_kernel(ForceArgs a) {
 #pragma unroll
     for (int k = 0; k < IPT; ++k) {
         const int ii = ibase + k * WG + tid;
-        if (ii >= a.ni) continue;
+        if (ii >= iend) continue;
         float hi[7], lo[7];
 #pragma unroll
         for (int q = 0; q < 7; ++q) {
@@ -179,7 +178,7 @@ __global__ __launch_bounds__(WG) void force_kernel(ForceArgs a) {
             lo[q] = PREC == 1 ? clo[k][q] : 0.f;
         }
         if (a.partial) {
-            const size_t base = (size_t)blockIdx.y * 7 * a.ni + ii;
+            const size_t base = (size_t)split * 7 * a.ni + ii;
 #pragma unroll
             for (int q = 0; q < 7; ++q) a.part[base + (size_t)q * a.ni] = make_float2(hi[q], lo[q]);
         } else {
@@ -196,6 +195,38 @@ __global__ __launch_bounds__(WG) void force_kernel(ForceArgs a) {
             for (int q = 0; q < 6; ++q) a.out[q][ii] = a.G * ((double)hi[q] + (double)lo[q]);
             a.out[6][ii] = -a.G * pot;
         }
+    }
+}
+
+template <int PREC, int IPT, int TJ, int WG, bool EPS0>
+__global__ __launch_bounds__(WG) void force_kernel(ForceArgs a) {
+    __shared__ float4 sh[2][TJ * Rec<PREC>::R];
+    const int jb = blockIdx.y * a.jchunk;
+    const int je = min(a.nj, jb + a.jchunk);
+    force_block<PREC, IPT, TJ, WG, EPS0>(a, sh, blockIdx.x * (WG * IPT), a.ni, jb, je, a.eps2, blockIdx.y);
+}
+
+// Many independent clusters in one persistent launch.  Work items
+// (cluster, i-block) come from the plan, largest clusters first; each
+// work-group takes the next item from a device counter until none is left.
+// Within a cluster every particle is both an i and a j (self excluded);
+// there are no cross-cluster terms.
+template <int PREC, int IPT, int TJ, int WG>
+__global__ __launch_bounds__(WG) void force_batched_kernel(ForceArgs a, BatchArgs b) {
+    __shared__ float4 sh[2][TJ * Rec<PREC>::R];
+    __shared__ int item_sh;
+    const int n_items = *b.n_items;
+    for (;;) {
+        if (threadIdx.x == 0) item_sh = atomicAdd(b.counter, 1);
+        __syncthreads();
+        const int item = item_sh;
+        __syncthreads();
+        if (item >= n_items) break;
+        const int2 it = b.items[item];
+        const int beg = b.cbeg[it.x], end = b.cend[it.x];
+        const double e = b.eps[it.x];
+        force_block<PREC, IPT, TJ, WG, false>(a, sh, beg + it.y * (WG * IPT), end, beg, end,
+                                              (float)(e * e), 0);
     }
 }
 
@@ -303,6 +334,62 @@ hipError_t launch_predict_all(int n, const double* const* s, const int64_t* t, c
     return hipGetLastError();
 }
 
+// Plan: one work-group orders the clusters by size (largest first), splits
+// each into i-blocks of `per` particles and writes the (cluster, block) items
+// and their count.  Cluster ranges are clamped to [0, n_total] so that
+// inconsistent offsets can never send a kernel out of bounds; items beyond
+// the table capacity are dropped.
+__global__ __launch_bounds__(1024) void batch_plan_kernel(PlanArgs p) {
+    const int tid = threadIdx.x;
+    const int C = p.n_clusters;
+    for (int c = tid; c < C; c += 1024) {
+        int64_t lo = p.offsets[c], hi = p.offsets[c + 1];
+        lo = lo < 0 ? 0 : (lo > p.n_total ? p.n_total : lo);
+        hi = hi < lo ? lo : (hi > p.n_total ? p.n_total : hi);
+        p.cbeg[c] = (int)lo;
+        p.cend[c] = (int)hi;
+    }
+    __syncthreads();
+    // rank by size, descending; ties by index (a permutation)
+    for (int c = tid; c < C; c += 1024) {
+        const int sz = p.cend[c] - p.cbeg[c];
+        int r = 0;
+        if (C <= 16384) {
+            for (int d = 0; d < C; ++d) {
+                const int sd = p.cend[d] - p.cbeg[d];
+                r += (sd > sz || (sd == sz && d < c)) ? 1 : 0;
+            }
+        } else {
+            r = c;
+        }
+        p.order[r] = c;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        int64_t acc = 0;
+        for (int r = 0; r < C; ++r) {
+            const int c = p.order[r];
+            p.start[r] = (int)acc;
+            acc += (p.cend[c] - p.cbeg[c] + p.per - 1) / p.per;
+        }
+        *p.n_items = (int)(acc < p.cap ? acc : p.cap);
+    }
+    __syncthreads();
+    for (int r = tid; r < C; r += 1024) {
+        const int c = p.order[r];
+        const int nb = (p.cend[c] - p.cbeg[c] + p.per - 1) / p.per;
+        for (int k = 0; k < nb; ++k) {
+            const int64_t slot = (int64_t)p.start[r] + k;
+            if (slot < p.cap) p.items[slot] = make_int2(c, k);
+        }
+    }
+}
+
+hipError_t launch_batch_plan(const PlanArgs& p, hipStream_t st) {
+    hipLaunchKernelGGL(batch_plan_kernel, dim3(1), dim3(1024), 0, st, p);
+    return hipGetLastError();
+}
+
 // ---- variant table -----------------------------------------------------------
 
 template <int PREC, int IPT, int TJ, int WG, bool EPS0>
@@ -311,15 +398,24 @@ static hipError_t launch_one(int nb, int S, const ForceArgs& a, hipStream_t st) 
     return hipGetLastError();
 }
 
+template <int PREC, int IPT, int TJ, int WG, bool EPS0>
+static hipError_t launch_batched_one(int grid, const ForceArgs& a, const BatchArgs& b, hipStream_t st) {
+    if (EPS0) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((force_batched_kernel<PREC, IPT, TJ, WG>), dim3(grid), dim3(WG), 0, st, a, b);
+    return hipGetLastError();
+}
+
 typedef hipError_t (*LaunchFn)(int, int, const ForceArgs&, hipStream_t);
+typedef hipError_t (*BatchedFn)(int, const ForceArgs&, const BatchArgs&, hipStream_t);
 
 struct Variant {
     int prec, ipt, tj, wg;
     bool eps0;
     LaunchFn fn;
+    BatchedFn bfn;
 };
 
-#define NB_V(P, I, T, W, E) {P, I, T, W, E, &launch_one<P, I, T, W, E>}
+#define NB_V(P, I, T, W, E) {P, I, T, W, E, &launch_one<P, I, T, W, E>, &launch_batched_one<P, I, T, W, E>}
 #define NB_VT(P, I, W)                                                                  \
     NB_V(P, I, 64, W, false), NB_V(P, I, 128, W, false), NB_V(P, I, 256, W, false)
 #define NB_VW(P, I) NB_VT(P, I, 128), NB_VT(P, I, 256)
@@ -348,6 +444,13 @@ hipError_t launch_force(int prec, int ipt, int tj, int wg, bool eps0, int nb, in
     const Variant* v = find_variant(prec, ipt, tj, wg, eps0);
     if (!v) return hipErrorInvalidValue;
     return v->fn(nb, S, a, st);
+}
+
+hipError_t launch_force_batched(int prec, int ipt, int tj, int wg, int grid, const ForceArgs& a,
+                                const BatchArgs& b, hipStream_t st) {
+    const Variant* v = find_variant(prec, ipt, tj, wg, false);
+    if (!v) return hipErrorInvalidValue;
+    return v->bfn(grid, a, b, st);
 }
 
 }  // namespace nb

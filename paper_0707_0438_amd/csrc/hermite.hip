@@ -203,4 +203,15 @@ hipError_t launch_fill_i64(int64_t* p, int n, int64_t v, hipStream_t st) {
     return hipGetLastError();
 }
 
+__global__ __launch_bounds__(256) void fill_i32_kernel(int* p, int n, int v) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+hipError_t launch_fill_i32(int* p, int n, int v, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_i32_kernel, dim3((n + 255) / 256), dim3(256), 0, st, p, n, v);
+    return hipGetLastError();
+}
+
 }  // namespace nb

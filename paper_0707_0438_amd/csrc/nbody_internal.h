@@ -55,6 +55,29 @@ hipError_t launch_force(int prec, int ipt, int tile_j, int wg, bool eps0, int n_
 bool force_variant_exists(int prec, int ipt, int tile_j, int wg, bool eps0);
 hipError_t launch_reduce(const ReduceArgs& a, hipStream_t st);
 
+// ---- batched clusters ----
+struct BatchArgs {
+    const int2* items;       // (cluster, i-block)
+    const int* n_items;      // device scalar
+    int* counter;            // device work counter (zeroed before the launch)
+    const int* cbeg;         // clamped cluster ranges
+    const int* cend;
+    const double* eps;       // per-cluster softening
+};
+struct PlanArgs {
+    int n_clusters;
+    const int64_t* offsets;  // device [n_clusters + 1]
+    int n_total;
+    int per;                 // i-particles per work item (WG * IPT)
+    int64_t cap;             // item table capacity
+    int *cbeg, *cend, *order, *start, *n_items;
+    int2* items;
+};
+hipError_t launch_batch_plan(const PlanArgs& p, hipStream_t st);
+hipError_t launch_force_batched(int prec, int ipt, int tile_j, int wg, int grid, const ForceArgs& a,
+                                const BatchArgs& b, hipStream_t st);
+hipError_t launch_fill_i32(int* p, int n, int v, hipStream_t st);
+
 // Pack float64 rows into records; with t != NULL every particle is first
 // predicted to the block time *tnext (device) by the Hermite predictor.
 struct PackArgs {
