@@ -143,6 +143,58 @@ def adjoint_timing(nb, ctx, prec, reps=10):
             "backward_over_forward": round(t_adj / t_run, 3)}
 
 
+def batched_timing(ctx, prec, steps=32):
+    """512 independent Plummer clusters (N_c log-uniform in [64, 8192],
+    eps_c = 1/(4 N_c^(1/3))), 32 shared Hermite steps of 1/256: one captured
+    hipGraph against the same steps launched eagerly and against one
+    shared-step run per cluster.  The launch shape is picked by the batched
+    autotuner first."""
+    import numpy as np
+    import torch
+    import nbody_inputs as ics
+    off, eps, p = ics.clusters(512, ics.seed_for(4))
+    n = p.n
+    sizes = np.diff(off)
+    inter_step = float((sizes.astype(np.float64) ** 2).sum())
+    X = torch.from_numpy(p.pos).to("cuda")
+    V = torch.from_numpy(p.vel).to("cuda")
+    M = torch.from_numpy(p.mass).to("cuda")
+    O = torch.from_numpy(off).to("cuda")
+    E = torch.from_numpy(eps).to("cuda")
+    tile, tile_ms = ctx.autotune_batched(X, V, M, O, E, prec=prec, reps=3)
+    a0, j0, _ = ctx.force_batched(X, V, M, O, E, prec=prec)
+    dt = 1.0 / 256
+
+    def run(mode):
+        x, v, a, j = X.clone(), V.clone(), a0.clone(), j0.clone()
+        ctx.batch_hermite(x, v, a, j, M, O, E, dt, steps, prec=prec, use_graph=(mode == "graph"))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.batch_hermite(x, v, a, j, M, O, E, dt, steps, prec=prec, use_graph=(mode == "graph"))
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    t_graph = run("graph")
+    t_eager = run("eager")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for c in range(len(sizes)):
+        lo, hi = int(off[c]), int(off[c + 1])
+        ctx.shared_run(X[:, lo:hi].contiguous(), V[:, lo:hi].contiguous(), M[lo:hi].contiguous(),
+                       float(eps[c]), dt, steps, prec=prec, checkpoints=False)
+    torch.cuda.synchronize()
+    t_per = time.perf_counter() - t0
+    tot = inter_step * steps
+    return {"workload": "clusters512_batched: 512 Plummer clusters, N_c log-uniform in [64, 8192] "
+                        f"(total {n} particles, sum N_c^2 = {inter_step:.4g}), eps_c = 1/(4 N_c^(1/3)); "
+                        "32 shared Hermite steps of 1/256",
+            "tile": tile, "autotuned_force_ms": round(tile_ms, 3),
+            "graph_ms": round(t_graph * 1e3, 2), "eager_ms": round(t_eager * 1e3, 2),
+            "per_cluster_ms": round(t_per * 1e3, 2),
+            "graph_Gint_s": round(tot / t_graph / 1e9, 1), "eager_Gint_s": round(tot / t_eager / 1e9, 1),
+            "per_cluster_Gint_s": round(tot / t_per / 1e9, 1)}
+
+
 def copy_calibration(nbytes=1 << 30, reps=4):
     """A plain device-to-device copy of `nbytes` (read nbytes + write nbytes
     per launch), to scale the HBM counters of the force kernel."""
@@ -261,6 +313,8 @@ def main():
             "kernel_ms": round(o["kms"] / max(o["launches"], 1), 3),
             "pct_fp32_peak": round(100.0 * FLOPS_PER_INTERACTION * ov * 1e9 / (FP32_PEAK_TFLOPS * 1e12), 2),
         }
+    log("[bench] batched clusters")
+    line["batched"] = batched_timing(ctx, args.prec)
     log("[bench] adjoint/forward timing")
     line["adjoint"] = adjoint_timing(nb, ctx, args.prec)
     if args.cpu_budget > 0:

@@ -21,13 +21,17 @@ def ctx():
 
 
 def small_clusters(seed, sizes):
-    parts = [ics.plummer(int(s), seed * 100 + k) for k, s in enumerate(sizes)]
+    def one(s, k):
+        if s == 0:
+            return ics.Particles(np.zeros((3, 0)), np.zeros((3, 0)), np.zeros(0))
+        return ics.plummer(int(s), seed * 100 + k)
+    parts = [one(s, k) for k, s in enumerate(sizes)]
     off = np.zeros(len(sizes) + 1, dtype=np.int64)
     off[1:] = np.cumsum(sizes)
     pos = np.concatenate([p.pos for p in parts], axis=1)
     vel = np.concatenate([p.vel for p in parts], axis=1)
     m = np.concatenate([p.mass for p in parts])
-    eps = 1.0 / (4.0 * np.asarray(sizes, dtype=np.float64) ** (1.0 / 3.0))
+    eps = 1.0 / (4.0 * np.maximum(np.asarray(sizes, dtype=np.float64), 1.0) ** (1.0 / 3.0))
     return off, eps, pos, vel, m
 
 
