@@ -80,14 +80,24 @@ typedef struct {
 } nbody_out;
 
 /* Launch shape of the pairwise kernel (also the autotuner's search space).
- *  tile_j: j-particles staged in LDS per tile, one of 64, 128, 256.
+ *  tile_j: j-particles per tile (staged in LDS when jsrc = 0; the interval
+ *          between compensated folds when jsrc = 1): 64, 128, 256
+ *          (jsrc = 1: 128).
  *  ipt:    i-particles held in registers per lane, one of 1, 2, 4.
- *  wg:     work-group size in lanes, one of 128, 256.
+ *  wg:     work-group size in lanes: 128 or 256 (jsrc = 1: 64 or 256).
  *  split:  number of j-ranges the j set is cut into (>= 1; 0 = choose
  *          from the shape); partial sums are reduced in float64 in fixed
- *          order (Section 3.2). */
+ *          order (Section 3.2).
+ *  jsrc:   0 = j records staged tile by tile in LDS (Section 3.1, Fig. 1);
+ *          1 = j records read by wave-uniform loads through the scalar data
+ *          cache (no LDS, no barrier).
+ *  unroll: unroll depth of the j loop (0 = the default 4).
+ *  waves:  waves per SIMD requested from the compiler, a register cap
+ *          (0 = none).
+ * Only the shapes compiled into the library exist; nbody_set_tile rejects
+ * others and nbody_autotune visits all of them. */
 typedef struct {
-    int tile_j, ipt, wg, split;
+    int tile_j, ipt, wg, split, jsrc, unroll, waves;
 } nbody_tile;
 
 /* ---- context ------------------------------------------------------------ */
@@ -121,8 +131,8 @@ int nbody_abi_version(void);
 int nbody_kernel_timing(nbody_ctx *ctx, int enable);
 int nbody_kernel_time(nbody_ctx *ctx, double *total_ms, int64_t *launches);
 
-/* Force the launch shape used for `prec` (all fields > 0 except split,
- * which may be 0), or clear the override when t is NULL. */
+/* Force the launch shape used for `prec` (a shape that exists, see
+ * nbody_tile; split may be 0), or clear the override when t is NULL. */
 int nbody_set_tile(nbody_ctx *ctx, nbody_prec prec, const nbody_tile *t);
 
 /* The launch shape the next nbody_force call would use for this shape. */

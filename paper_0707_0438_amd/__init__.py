@@ -56,10 +56,12 @@ class Out(C.Structure):
 
 
 class Tile(C.Structure):
-    _fields_ = [("tile_j", C.c_int), ("ipt", C.c_int), ("wg", C.c_int), ("split", C.c_int)]
+    _fields_ = [("tile_j", C.c_int), ("ipt", C.c_int), ("wg", C.c_int), ("split", C.c_int),
+                ("jsrc", C.c_int), ("unroll", C.c_int), ("waves", C.c_int)]
 
     def as_dict(self):
-        return {"tile_j": self.tile_j, "ipt": self.ipt, "wg": self.wg, "split": self.split}
+        return {"tile_j": self.tile_j, "ipt": self.ipt, "wg": self.wg, "split": self.split,
+                "jsrc": self.jsrc, "unroll": self.unroll, "waves": self.waves}
 
 
 class HermiteOpts(C.Structure):
@@ -242,12 +244,12 @@ class Context:
     def reserve(self, max_i, max_j):
         self._check(lib().nbody_reserve(self._h, int(max_i), int(max_j)), "nbody_reserve")
 
-    def set_tile(self, prec="ds", tile_j=None, ipt=None, wg=None, split=0):
+    def set_tile(self, prec="ds", tile_j=None, ipt=None, wg=None, split=0, jsrc=0, unroll=0, waves=0):
         p = PREC[prec]
         if tile_j is None:
             self._check(lib().nbody_set_tile(self._h, p, None), "nbody_set_tile")
         else:
-            t = Tile(int(tile_j), int(ipt), int(wg), int(split))
+            t = Tile(int(tile_j), int(ipt), int(wg), int(split), int(jsrc), int(unroll), int(waves))
             self._check(lib().nbody_set_tile(self._h, p, C.byref(t)), "nbody_set_tile")
 
     def get_tile(self, n_i, n_j, prec="ds"):

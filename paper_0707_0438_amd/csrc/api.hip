@@ -143,10 +143,9 @@ static int check_out(nbody_ctx* c, const nbody_out& o) {
 }
 
 static bool valid_tile(const nbody_tile& t) {
-    const bool tj = t.tile_j == 64 || t.tile_j == 128 || t.tile_j == 256;
-    const bool ip = t.ipt == 1 || t.ipt == 2 || t.ipt == 4;
-    const bool wg = t.wg == 128 || t.wg == 256;
-    return tj && ip && wg && t.split >= 0 && t.split <= 4096;
+    if (t.split < 0 || t.split > 4096 || (t.jsrc != 0 && t.jsrc != 1)) return false;
+    return force_variant_exists(0, t.ipt, t.tile_j, t.wg, t.jsrc, t.unroll, t.waves, false) ||
+           force_variant_exists(1, t.ipt, t.tile_j, t.wg, t.jsrc, t.unroll, t.waves, false);
 }
 
 // Number of j-ranges for an i-list of ni against nj: enough work-groups to
@@ -162,12 +161,20 @@ static int choose_split(int64_t ni, int64_t nj, const nbody_tile& t) {
     return (int)std::max<int64_t>(1, S);
 }
 
-static nbody_tile default_tile(int prec, int64_t ni) {
+// Default launch shape when neither an override nor a tuned entry exists:
+// the fastest shape of the MI355X sweep at 2^20 x 2^20 (one i per lane,
+// 256-record LDS tiles, software-pipelined LDS reads) for large problems,
+// 64-record tiles for small ones (more j-ranges to spread over the CUs).
+static nbody_tile default_tile(int prec, int64_t ni, int64_t nj) {
     nbody_tile t;
-    t.tile_j = 128;
+    const bool large = (double)ni * (double)nj >= 4294967296.0;
+    t.tile_j = large ? 256 : 64;
     t.wg = 256;
-    t.ipt = ni >= 65536 ? 2 : 1;
+    t.ipt = 1;
     t.split = 0;
+    t.jsrc = 0;
+    t.unroll = large ? 102 : 0;
+    t.waves = 0;
     (void)prec;
     return t;
 }
@@ -177,7 +184,7 @@ static nbody_tile pick_tile(nbody_ctx* c, int prec, int64_t ni, int64_t nj) {
     if (c->have_override[prec]) {
         t = c->override_tile[prec];
     } else if (!c->tune.lookup(prec, ni, nj, &t)) {
-        t = default_tile(prec, ni);
+        t = default_tile(prec, ni, nj);
     }
     if (t.split <= 0) t.split = choose_split(ni, nj, t);
     return t;
@@ -191,11 +198,15 @@ static int run_force(nbody_ctx* c, hipStream_t st, int prec, double G, double ep
     nbody_tile t = forced ? *forced : pick_tile(c, prec, ni, nj);
     if (t.split <= 0) t.split = choose_split(ni, nj, t);
     const bool eps0 = eps == 0.0;
-    int ipt = t.ipt, tj = t.tile_j, wg = t.wg;
-    if (eps0 && !force_variant_exists(prec, ipt, tj, wg, true)) {
+    int ipt = t.ipt, tj = t.tile_j, wg = t.wg, jsrc = t.jsrc, unr = t.unroll, wpe = t.waves;
+    if (!force_variant_exists(prec, ipt, tj, wg, jsrc, unr, wpe, eps0)) {
+        // the unsoftened path exists in one LDS shape per precision
         ipt = ipt >= 2 ? 2 : 1;
         tj = 128;
         wg = 256;
+        jsrc = 0;
+        unr = 0;
+        wpe = 0;
     }
     const int64_t per_blk = (int64_t)wg * ipt;
     const int nb = (int)((ni + per_blk - 1) / per_blk);
@@ -234,7 +245,7 @@ static int run_force(nbody_ctx* c, hipStream_t st, int prec, double G, double ep
         c->ev_used += 2;
         if (hipEventRecord(tb, st) != hipSuccess) return set_err(c, NBODY_ERR_DEVICE, "event record");
     }
-    hipError_t e = launch_force(prec, ipt, tj, wg, eps0, nb, S, a, st);
+    hipError_t e = launch_force(prec, ipt, tj, wg, jsrc, unr, wpe, eps0, nb, S, a, st);
     if (e != hipSuccess) return hip_err(c, e, "force kernel launch");
     if (te && hipEventRecord(te, st) != hipSuccess) return set_err(c, NBODY_ERR_DEVICE, "event record");
     if (S > 1) {
@@ -400,8 +411,8 @@ int nbody_set_tile(nbody_ctx* c, nbody_prec prec, const nbody_tile* t) {
         return NBODY_OK;
     }
     if (!valid_tile(*t))
-        return set_err(c, NBODY_ERR_ARG, "tile (tile_j=%d ipt=%d wg=%d split=%d) not supported", t->tile_j,
-                       t->ipt, t->wg, t->split);
+        return set_err(c, NBODY_ERR_ARG, "tile (tile_j=%d ipt=%d wg=%d split=%d jsrc=%d unroll=%d waves=%d) not supported",
+                       t->tile_j, t->ipt, t->wg, t->split, t->jsrc, t->unroll, t->waves);
     c->override_tile[prec] = *t;
     c->have_override[prec] = true;
     return NBODY_OK;
@@ -1136,7 +1147,15 @@ static nbody_tile batched_tile(nbody_ctx* c, int prec, int64_t n_total, int32_t 
         t.ipt = 1;
         t.wg = 128;
         t.split = 1;
+        t.jsrc = 0;
     }
+    if (t.jsrc != 0 || t.unroll != 0 || t.waves != 0 || !force_variant_exists(prec, t.ipt, t.tile_j, t.wg, 0, 4, 0, false)) {
+        t.tile_j = 128;
+        t.jsrc = 0;
+        if (t.wg != 128 && t.wg != 256) t.wg = 256;
+    }
+    t.unroll = 0;
+    t.waves = 0;
     t.split = 1;
     return t;
 }
@@ -1396,7 +1415,7 @@ int nbody_autotune_batched(nbody_ctx* c, hipStream_t st, nbody_prec prec, double
     for (int a = 0; a < 3 && !rc; ++a)
         for (int b = 0; b < 3 && !rc; ++b)
             for (int wi = 0; wi < 2 && !rc; ++wi) {
-                nbody_tile t{tjs[a], ipts[b], wgs[wi], 1};
+                nbody_tile t{tjs[a], ipts[b], wgs[wi], 1, 0, 0, 0};
                 c->override_tile[p] = t;
                 c->have_override[p] = true;
                 rc = nbody_force_batched(c, st, prec, G, n_clusters, offsets, eps, n_total, P, out);
@@ -1459,13 +1478,19 @@ int nbody_autotune(nbody_ctx* c, hipStream_t st, nbody_prec prec, double G, doub
         (void)hipEventDestroy(e0);
         return set_err(c, NBODY_ERR_DEVICE, "event create");
     }
-    const int tjs[3] = {64, 128, 256}, ipts[3] = {1, 2, 4}, wgs[2] = {128, 256};
+    std::vector<nbody_tile> cand;
+    for (int k = 0; k < force_variant_count(); ++k) {
+        int vp, vi, vt, vw, vj, vu, vo;
+        bool ve;
+        if (force_variant_at(k, &vp, &vi, &vt, &vw, &vj, &vu, &vo, &ve) && vp == p && ve == (eps == 0.0))
+            cand.push_back(nbody_tile{vt, vi, vw, 0, vj, vu, vo});
+    }
     nbody_tile bt{};
     double bms = 1e300;
-    for (int a = 0; a < 3 && !rc; ++a)
-        for (int b = 0; b < 3 && !rc; ++b)
-            for (int w = 0; w < 2 && !rc; ++w) {
-                nbody_tile t{tjs[a], ipts[b], wgs[w], 0};
+    for (size_t ci = 0; ci < cand.size() && !rc; ++ci) {
+            {
+                nbody_tile t = cand[ci];
+
                 t.split = choose_split(n_i, n_j, t);
                 rc = run_force(c, st, p, G, eps, n_i, ip, nullptr, nullptr, 0, n_j, (const float4*)c->jpack.p, o, &t);
                 if (rc) break;
@@ -1487,6 +1512,7 @@ int nbody_autotune(nbody_ctx* c, hipStream_t st, nbody_prec prec, double G, doub
                     bt = t;
                 }
             }
+    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (rc) return rc;

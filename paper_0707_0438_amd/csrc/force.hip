@@ -47,7 +47,7 @@ __device__ __forceinline__ void two_sum_fold(float& hi, float& lo, float p) {
 // One work-group's share: i slots ibase + k*WG + tid (k < IPT) below iend,
 // against j in [jb, je).  Results go to the float64 outputs (with the
 // self-potential removal) or to split partial slot `split`.
-template <int PREC, int IPT, int TJ, int WG, bool EPS0>
+template <int PREC, int IPT, int TJ, int WG, bool EPS0, bool JS = false, int UNR = 4, bool PIPE = false>
 __device__ __forceinline__ void force_block(const ForceArgs& a, float4 (*sh)[TJ * Rec<PREC>::R], int ibase,
                                             int iend, int jb, int je, float eps2, int split) {
     constexpr int R = Rec<PREC>::R;
@@ -107,52 +107,42 @@ __device__ __forceinline__ void force_block(const ForceArgs& a, float4 (*sh)[TJ 
         }
     };
 
-    if (ntiles > 0) {
-        load_tile(0);
-        store_tile(0);
-    }
-    __syncthreads();
-
-    for (int t = 0; t < ntiles; ++t) {
-        const int buf = t & 1;
-        if (t + 1 < ntiles) load_tile(t + 1);
-        const float4* tile = sh[buf];
-#pragma unroll 4
-        for (int jj = 0; jj < TJ; ++jj) {
-            const float4 q0 = tile[jj * R + 0];
-            const float4 q1 = tile[jj * R + 1];
-            float4 q2;
-            if (PREC == 1) q2 = tile[jj * R + 2];
+    // eps^2 lives in a VGPR: an SGPR operand would halve the issue rate of
+    // the instruction that reads it
+    float eps2v;
+    asm volatile("v_mov_b32 %0, %1" : "=v"(eps2v) : "s"(eps2));
+    auto interact = [&](const float4& q0, const float4& q1, const float4& q2) {
 #pragma unroll
-            for (int k = 0; k < IPT; ++k) {
-                float dx, dy, dz;
-                if (PREC == 1) {
-                    dx = (q0.x - ix[k]) + (q2.x - lx[k]);
-                    dy = (q0.y - iy[k]) + (q2.y - ly[k]);
-                    dz = (q0.z - iz[k]) + (q2.z - lz[k]);
-                } else {
-                    dx = q0.x - ix[k];
-                    dy = q0.y - iy[k];
-                    dz = q0.z - iz[k];
-                }
-                const float ux = q1.x - iu[k], uy = q1.y - iv[k], uz = q1.z - iw[k];
-                const float s = fmaf(dz, dz, fmaf(dy, dy, fmaf(dx, dx, eps2)));
-                const float rv = fmaf(dz, uz, fmaf(dy, uy, dx * ux));
-                float rinv = __builtin_amdgcn_rsqf(s);
-                if (EPS0) rinv = s > 0.f ? rinv : 0.f;
-                const float rinv2 = rinv * rinv;
-                const float mr = q0.w * rinv;
-                const float mr3 = mr * rinv2;
-                const float al = 3.0f * rv * rinv2;
-                acc[k][0] = fmaf(mr3, dx, acc[k][0]);
-                acc[k][1] = fmaf(mr3, dy, acc[k][1]);
-                acc[k][2] = fmaf(mr3, dz, acc[k][2]);
-                acc[k][3] = fmaf(mr3, fmaf(-al, dx, ux), acc[k][3]);
-                acc[k][4] = fmaf(mr3, fmaf(-al, dy, uy), acc[k][4]);
-                acc[k][5] = fmaf(mr3, fmaf(-al, dz, uz), acc[k][5]);
-                acc[k][6] += mr;
+        for (int k = 0; k < IPT; ++k) {
+            float dx, dy, dz;
+            if (PREC == 1) {
+                dx = (q0.x - ix[k]) + (q2.x - lx[k]);
+                dy = (q0.y - iy[k]) + (q2.y - ly[k]);
+                dz = (q0.z - iz[k]) + (q2.z - lz[k]);
+            } else {
+                dx = q0.x - ix[k];
+                dy = q0.y - iy[k];
+                dz = q0.z - iz[k];
             }
+            const float ux = q1.x - iu[k], uy = q1.y - iv[k], uz = q1.z - iw[k];
+            const float s = fmaf(dz, dz, fmaf(dy, dy, fmaf(dx, dx, eps2v)));
+            const float rv = fmaf(dz, uz, fmaf(dy, uy, dx * ux));
+            float rinv = __builtin_amdgcn_rsqf(s);
+            if (EPS0) rinv = s > 0.f ? rinv : 0.f;
+            const float rinv2 = rinv * rinv;
+            const float mr = q0.w * rinv;
+            const float mr3 = mr * rinv2;
+            const float al = 3.0f * rv * rinv2;
+            acc[k][0] = fmaf(mr3, dx, acc[k][0]);
+            acc[k][1] = fmaf(mr3, dy, acc[k][1]);
+            acc[k][2] = fmaf(mr3, dz, acc[k][2]);
+            acc[k][3] = fmaf(mr3, fmaf(-al, dx, ux), acc[k][3]);
+            acc[k][4] = fmaf(mr3, fmaf(-al, dy, uy), acc[k][4]);
+            acc[k][5] = fmaf(mr3, fmaf(-al, dz, uz), acc[k][5]);
+            acc[k][6] += mr;
         }
+    };
+    auto fold = [&]() {
         if (PREC == 1) {
 #pragma unroll
             for (int k = 0; k < IPT; ++k)
@@ -162,8 +152,67 @@ __device__ __forceinline__ void force_block(const ForceArgs& a, float4 (*sh)[TJ 
                     acc[k][q] = 0.f;
                 }
         }
-        if (t + 1 < ntiles) store_tile(buf ^ 1);
+    };
+
+    if (JS) {
+        // j records read by wave-uniform loads (scalar data cache); chunks of
+        // TJ j between compensated folds; no LDS, no barrier
+        const float4* __restrict__ jp = a.jpack;
+        for (int j0 = jb; j0 < je; j0 += TJ) {
+            const int j1 = min(je, j0 + TJ);
+#pragma unroll UNR
+            for (int j = j0; j < j1; ++j) {
+                const float4 q0 = jp[(size_t)j * R + 0];
+                const float4 q1 = jp[(size_t)j * R + 1];
+                float4 q2 = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (PREC == 1) q2 = jp[(size_t)j * R + 2];
+                interact(q0, q1, q2);
+            }
+            fold();
+        }
+    } else {
+        if (ntiles > 0) {
+            load_tile(0);
+            store_tile(0);
+        }
         __syncthreads();
+
+        for (int t = 0; t < ntiles; ++t) {
+            const int buf = t & 1;
+            if (t + 1 < ntiles) load_tile(t + 1);
+            const float4* tile = sh[buf];
+            if (PIPE) {
+                // software pipeline: the record of j+1 is read from LDS while
+                // j is being computed
+                float4 q0 = tile[0], q1 = tile[1];
+                float4 q2 = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (PREC == 1) q2 = tile[2];
+#pragma unroll UNR
+                for (int jj = 0; jj < TJ; ++jj) {
+                    const int jn = jj + 1 < TJ ? jj + 1 : jj;
+                    const float4 n0 = tile[jn * R + 0];
+                    const float4 n1 = tile[jn * R + 1];
+                    float4 n2 = make_float4(0.f, 0.f, 0.f, 0.f);
+                    if (PREC == 1) n2 = tile[jn * R + 2];
+                    interact(q0, q1, q2);
+                    q0 = n0;
+                    q1 = n1;
+                    q2 = n2;
+                }
+            } else {
+#pragma unroll UNR
+                for (int jj = 0; jj < TJ; ++jj) {
+                    const float4 q0 = tile[jj * R + 0];
+                    const float4 q1 = tile[jj * R + 1];
+                    float4 q2 = make_float4(0.f, 0.f, 0.f, 0.f);
+                    if (PREC == 1) q2 = tile[jj * R + 2];
+                    interact(q0, q1, q2);
+                }
+            }
+            fold();
+            if (t + 1 < ntiles) store_tile(buf ^ 1);
+            __syncthreads();
+        }
     }
 
     // epilogue
@@ -198,12 +247,28 @@ __device__ __forceinline__ void force_block(const ForceArgs& a, float4 (*sh)[TJ 
     }
 }
 
-template <int PREC, int IPT, int TJ, int WG, bool EPS0>
-__global__ __launch_bounds__(WG) void force_kernel(ForceArgs a) {
+// WPE > 0 asks the compiler for at least WPE waves per SIMD (a register cap);
+// UNR >= 100 selects the software-pipelined LDS loop with unroll UNR - 100.
+template <int PREC, int IPT, int TJ, int WG, bool EPS0, int UNR, int WPE>
+__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(WPE > 0 ? WPE : 1)))
+void force_kernel(ForceArgs a) {
     __shared__ float4 sh[2][TJ * Rec<PREC>::R];
     const int jb = blockIdx.y * a.jchunk;
     const int je = min(a.nj, jb + a.jchunk);
-    force_block<PREC, IPT, TJ, WG, EPS0>(a, sh, blockIdx.x * (WG * IPT), a.ni, jb, je, a.eps2, blockIdx.y);
+    force_block<PREC, IPT, TJ, WG, EPS0, false, (UNR >= 100 ? UNR - 100 : UNR), (UNR >= 100)>(
+        a, sh, blockIdx.x * (WG * IPT), a.ni, jb, je, a.eps2, blockIdx.y);
+}
+
+// Same work with the j records read through the scalar data cache instead of
+// LDS (every lane of a wave needs the same j record, so one wave-uniform load
+// serves the wave).  TJ only sets the compensated-fold interval.
+template <int PREC, int IPT, int TJ, int WG, bool EPS0, int UNR, int WPE>
+__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(WPE > 0 ? WPE : 1)))
+void force_kernel_js(ForceArgs a) {
+    const int jb = blockIdx.y * a.jchunk;
+    const int je = min(a.nj, jb + a.jchunk);
+    force_block<PREC, IPT, TJ, WG, EPS0, true, UNR>(a, nullptr, blockIdx.x * (WG * IPT), a.ni, jb, je, a.eps2,
+                                                     blockIdx.y);
 }
 
 // Many independent clusters in one persistent launch.  Work items
@@ -392,9 +457,15 @@ hipError_t launch_batch_plan(const PlanArgs& p, hipStream_t st) {
 
 // ---- variant table -----------------------------------------------------------
 
-template <int PREC, int IPT, int TJ, int WG, bool EPS0>
+template <int PREC, int IPT, int TJ, int WG, bool EPS0, int UNR, int WPE>
 static hipError_t launch_one(int nb, int S, const ForceArgs& a, hipStream_t st) {
-    hipLaunchKernelGGL((force_kernel<PREC, IPT, TJ, WG, EPS0>), dim3(nb, S), dim3(WG), 0, st, a);
+    hipLaunchKernelGGL((force_kernel<PREC, IPT, TJ, WG, EPS0, UNR, WPE>), dim3(nb, S), dim3(WG), 0, st, a);
+    return hipGetLastError();
+}
+
+template <int PREC, int IPT, int TJ, int WG, bool EPS0, int UNR, int WPE>
+static hipError_t launch_one_js(int nb, int S, const ForceArgs& a, hipStream_t st) {
+    hipLaunchKernelGGL((force_kernel_js<PREC, IPT, TJ, WG, EPS0, UNR, WPE>), dim3(nb, S), dim3(WG), 0, st, a);
     return hipGetLastError();
 }
 
@@ -409,13 +480,16 @@ typedef hipError_t (*LaunchFn)(int, int, const ForceArgs&, hipStream_t);
 typedef hipError_t (*BatchedFn)(int, const ForceArgs&, const BatchArgs&, hipStream_t);
 
 struct Variant {
-    int prec, ipt, tj, wg;
+    int prec, ipt, tj, wg, jsrc, unr, wpe;
     bool eps0;
     LaunchFn fn;
     BatchedFn bfn;
 };
 
-#define NB_V(P, I, T, W, E) {P, I, T, W, E, &launch_one<P, I, T, W, E>, &launch_batched_one<P, I, T, W, E>}
+#define NB_V(P, I, T, W, E) \
+    {P, I, T, W, 0, 4, 0, E, &launch_one<P, I, T, W, E, 4, 0>, &launch_batched_one<P, I, T, W, E>}
+#define NB_X(P, I, T, W, U, O) {P, I, T, W, 0, U, O, false, &launch_one<P, I, T, W, false, U, O>, nullptr}
+#define NB_J(P, I, W) {P, I, 128, W, 1, 4, 0, false, &launch_one_js<P, I, 128, W, false, 4, 0>, nullptr}
 #define NB_VT(P, I, W)                                                                  \
     NB_V(P, I, 64, W, false), NB_V(P, I, 128, W, false), NB_V(P, I, 256, W, false)
 #define NB_VW(P, I) NB_VT(P, I, 128), NB_VT(P, I, 256)
@@ -424,33 +498,58 @@ struct Variant {
 static const Variant kVariants[] = {
     NB_VP(0),
     NB_VP(1),
+    // j records through the scalar data cache
+    NB_J(0, 1, 64), NB_J(0, 2, 64), NB_J(0, 4, 64), NB_J(0, 1, 256), NB_J(0, 2, 256), NB_J(0, 4, 256),
+    NB_J(1, 1, 64), NB_J(1, 2, 64), NB_J(1, 4, 64), NB_J(1, 1, 256), NB_J(1, 2, 256), NB_J(1, 4, 256),
+    // unroll depth and occupancy experiments around the best LDS shapes
+    NB_X(0, 1, 256, 256, 2, 0), NB_X(0, 1, 256, 256, 8, 0), NB_X(0, 1, 256, 256, 4, 6), NB_X(0, 1, 256, 256, 4, 8),
+    NB_X(0, 2, 256, 256, 1, 0), NB_X(0, 2, 256, 256, 2, 0), NB_X(0, 2, 256, 256, 2, 5), NB_X(0, 2, 128, 256, 2, 4),
+    NB_X(1, 1, 256, 256, 2, 0), NB_X(1, 1, 256, 256, 8, 0), NB_X(1, 1, 256, 256, 4, 6), NB_X(1, 1, 256, 256, 4, 8),
+    NB_X(1, 2, 256, 256, 1, 0), NB_X(1, 2, 256, 256, 2, 0), NB_X(1, 2, 256, 256, 2, 5), NB_X(1, 2, 128, 256, 2, 4),
+    // software-pipelined LDS reads (unroll = 100 + depth)
+    NB_X(0, 1, 256, 256, 102, 0), NB_X(0, 1, 256, 256, 104, 0), NB_X(0, 2, 256, 256, 101, 0),
+    NB_X(1, 1, 256, 256, 102, 0), NB_X(1, 1, 256, 256, 104, 0), NB_X(1, 2, 256, 256, 101, 0),
+    NB_X(1, 1, 128, 256, 102, 0), NB_X(1, 1, 256, 128, 102, 0),
     // unsoftened (eps = 0) path: one shape per precision
     NB_V(0, 1, 128, 256, true), NB_V(0, 2, 128, 256, true),
     NB_V(1, 1, 128, 256, true), NB_V(1, 2, 128, 256, true),
 };
 
-static const Variant* find_variant(int prec, int ipt, int tj, int wg, bool eps0) {
+// unr / wpe of 0 select the default (unroll 4, no occupancy request)
+static const Variant* find_variant(int prec, int ipt, int tj, int wg, int jsrc, int unr, int wpe, bool eps0) {
+    if (unr == 0) unr = 4;
     for (const Variant& v : kVariants)
-        if (v.prec == prec && v.ipt == ipt && v.tj == tj && v.wg == wg && v.eps0 == eps0) return &v;
+        if (v.prec == prec && v.ipt == ipt && v.tj == tj && v.wg == wg && v.jsrc == jsrc && v.unr == unr &&
+            v.wpe == wpe && v.eps0 == eps0)
+            return &v;
     return nullptr;
 }
 
-bool force_variant_exists(int prec, int ipt, int tj, int wg, bool eps0) {
-    return find_variant(prec, ipt, tj, wg, eps0) != nullptr;
+bool force_variant_exists(int prec, int ipt, int tj, int wg, int jsrc, int unr, int wpe, bool eps0) {
+    return find_variant(prec, ipt, tj, wg, jsrc, unr, wpe, eps0) != nullptr;
 }
 
-hipError_t launch_force(int prec, int ipt, int tj, int wg, bool eps0, int nb, int S,
+hipError_t launch_force(int prec, int ipt, int tj, int wg, int jsrc, int unr, int wpe, bool eps0, int nb, int S,
                         const ForceArgs& a, hipStream_t st) {
-    const Variant* v = find_variant(prec, ipt, tj, wg, eps0);
+    const Variant* v = find_variant(prec, ipt, tj, wg, jsrc, unr, wpe, eps0);
     if (!v) return hipErrorInvalidValue;
     return v->fn(nb, S, a, st);
 }
 
 hipError_t launch_force_batched(int prec, int ipt, int tj, int wg, int grid, const ForceArgs& a,
                                 const BatchArgs& b, hipStream_t st) {
-    const Variant* v = find_variant(prec, ipt, tj, wg, false);
-    if (!v) return hipErrorInvalidValue;
+    const Variant* v = find_variant(prec, ipt, tj, wg, 0, 4, 0, false);
+    if (!v || !v->bfn) return hipErrorInvalidValue;
     return v->bfn(grid, a, b, st);
+}
+
+int force_variant_count() { return (int)(sizeof(kVariants) / sizeof(kVariants[0])); }
+
+bool force_variant_at(int k, int* prec, int* ipt, int* tj, int* wg, int* jsrc, int* unr, int* wpe, bool* eps0) {
+    if (k < 0 || k >= force_variant_count()) return false;
+    const Variant& v = kVariants[k];
+    *prec = v.prec; *ipt = v.ipt; *tj = v.tj; *wg = v.wg; *jsrc = v.jsrc; *unr = v.unr; *wpe = v.wpe; *eps0 = v.eps0;
+    return true;
 }
 
 }  // namespace nb

@@ -50,9 +50,13 @@ struct ReduceArgs {
 };
 
 // Launch the pairwise kernel for one configuration; returns hipError_t.
-hipError_t launch_force(int prec, int ipt, int tile_j, int wg, bool eps0, int n_iblocks, int S,
-                        const ForceArgs& a, hipStream_t st);
-bool force_variant_exists(int prec, int ipt, int tile_j, int wg, bool eps0);
+// jsrc 0: j tiles staged in LDS; 1: j records through wave-uniform scalar loads.
+// unr: unroll depth of the j loop (0 = 4); wpe: requested waves per SIMD (0 = none).
+hipError_t launch_force(int prec, int ipt, int tile_j, int wg, int jsrc, int unr, int wpe, bool eps0, int n_iblocks,
+                        int S, const ForceArgs& a, hipStream_t st);
+bool force_variant_exists(int prec, int ipt, int tile_j, int wg, int jsrc, int unr, int wpe, bool eps0);
+int force_variant_count();
+bool force_variant_at(int k, int* prec, int* ipt, int* tj, int* wg, int* jsrc, int* unr, int* wpe, bool* eps0);
 hipError_t launch_reduce(const ReduceArgs& a, hipStream_t st);
 
 // ---- batched clusters ----

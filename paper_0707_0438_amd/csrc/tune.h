@@ -61,7 +61,8 @@ class TuneCache {
     }
 
     // Lines look like
-    // {"arch": "gfx950", "prec": 1, "ni_log2": 20, "nj_log2": 20, "tile_j": 128, "ipt": 2, "wg": 256, "split": 1, "ms": 812.5}
+    // {"arch": "gfx950", "prec": 1, "ni_log2": 20, "nj_log2": 20, "tile_j": 128, "ipt": 2, "wg": 256,
+    //  "split": 1, "jsrc": 0, "unroll": 0, "waves": 0, "ms": 812.5}   (one line)
     void load() {
         if (path_.empty()) return;
         FILE* f = fopen(path_.c_str(), "r");
@@ -72,9 +73,11 @@ class TuneCache {
             Entry e{};
             const int got = sscanf(line,
                                    " {\"arch\": \"%63[^\"]\", \"prec\": %d, \"ni_log2\": %d, \"nj_log2\": %d, "
-                                   "\"tile_j\": %d, \"ipt\": %d, \"wg\": %d, \"split\": %d, \"ms\": %lf",
-                                   arch, &e.prec, &e.bi, &e.bj, &e.t.tile_j, &e.t.ipt, &e.t.wg, &e.t.split, &e.ms);
-            if (got == 9 && arch_ == arch) store_entry(e);
+                                   "\"tile_j\": %d, \"ipt\": %d, \"wg\": %d, \"split\": %d, \"jsrc\": %d, "
+                                   "\"unroll\": %d, \"waves\": %d, \"ms\": %lf",
+                                   arch, &e.prec, &e.bi, &e.bj, &e.t.tile_j, &e.t.ipt, &e.t.wg, &e.t.split, &e.t.jsrc,
+                                   &e.t.unroll, &e.t.waves, &e.ms);
+            if (got == 12 && arch_ == arch) store_entry(e);
         }
         fclose(f);
     }
@@ -87,8 +90,10 @@ class TuneCache {
         for (const Entry& e : entries_)
             fprintf(f,
                     "{\"arch\": \"%s\", \"prec\": %d, \"ni_log2\": %d, \"nj_log2\": %d, \"tile_j\": %d, "
-                    "\"ipt\": %d, \"wg\": %d, \"split\": %d, \"ms\": %.6f}\n",
-                    arch_.c_str(), e.prec, e.bi, e.bj, e.t.tile_j, e.t.ipt, e.t.wg, e.t.split, e.ms);
+                    "\"ipt\": %d, \"wg\": %d, \"split\": %d, \"jsrc\": %d, \"unroll\": %d, \"waves\": %d, "
+                    "\"ms\": %.6f}\n",
+                    arch_.c_str(), e.prec, e.bi, e.bj, e.t.tile_j, e.t.ipt, e.t.wg, e.t.split, e.t.jsrc, e.t.unroll,
+                    e.t.waves, e.ms);
         fclose(f);
         return rename(tmp.c_str(), path_.c_str()) == 0;
     }

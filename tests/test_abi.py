@@ -95,14 +95,18 @@ def test_other_entry_points_validate(hostctx):
     assert L.nbody_select_active(h, None, 5, None, 8, 8, C.byref(na), C.byref(tn)) == -1
     assert L.nbody_select_active(h, None, 5, 8, 8, 8, None, C.byref(tn)) == -1
     assert L.nbody_reserve(h, -5, 1) == -1
-    t = nb.Tile(100, 2, 256, 0)
+    t = nb.Tile(100, 2, 256, 0, 0, 0, 0)
     assert L.nbody_set_tile(h, 1, C.byref(t)) == -1
-    t = nb.Tile(128, 3, 256, 0)
+    t = nb.Tile(128, 3, 256, 0, 0, 0, 0)
     assert L.nbody_set_tile(h, 1, C.byref(t)) == -1
-    t = nb.Tile(128, 2, 256, 0)
+    t = nb.Tile(64, 2, 256, 0, 1, 0, 0)          # scalar-cache path exists with tile 128 only
+    assert L.nbody_set_tile(h, 1, C.byref(t)) == -1
+    t = nb.Tile(128, 2, 64, 0, 1, 0, 0)
     assert L.nbody_set_tile(h, 1, C.byref(t)) == 0
-    assert hostctx.get_tile(1000, 1000) == {"tile_j": 128, "ipt": 2, "wg": 256,
-                                            "split": hostctx.get_tile(1000, 1000)["split"]}
+    t = nb.Tile(128, 2, 256, 0, 0, 0, 0)
+    assert L.nbody_set_tile(h, 1, C.byref(t)) == 0
+    got = hostctx.get_tile(1000, 1000)
+    assert (got["tile_j"], got["ipt"], got["wg"], got["jsrc"]) == (128, 2, 256, 0)
     assert L.nbody_set_tile(h, 1, None) == 0
     hp = C.c_void_p()
     o = nb.HermiteOpts(1.0, 0.01, 0.02, 0.01, -20, -3, 0, 1)

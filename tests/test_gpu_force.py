@@ -67,18 +67,25 @@ def test_every_launch_shape_and_split(ctx, prec):
     ref = oracle.force(p.pos, p.vel, p.pos, p.vel, p.mass, eps, iself=np.arange(p.n))
     X, V, M = dev(p.pos), dev(p.vel), dev(p.mass)
     S = dev(np.arange(p.n, dtype=np.int32))
+    shapes = [(tj, ipt, wg, 0, 0, 0) for tj in (64, 128, 256) for ipt in (1, 2, 4) for wg in (128, 256)]
+    shapes += [(128, ipt, wg, 1, 0, 0) for ipt in (1, 2, 4) for wg in (64, 256)]
+    # unroll / occupancy / software-pipelined variants
+    shapes += [(256, 1, 256, 0, 2, 0), (256, 1, 256, 0, 8, 0), (256, 1, 256, 0, 4, 6), (256, 1, 256, 0, 4, 8),
+               (256, 2, 256, 0, 1, 0), (256, 2, 256, 0, 2, 0), (256, 2, 256, 0, 2, 5), (128, 2, 256, 0, 2, 4),
+               (256, 1, 256, 0, 102, 0), (256, 1, 256, 0, 104, 0), (256, 2, 256, 0, 101, 0)]
+    if prec == "ds":
+        shapes += [(128, 1, 256, 0, 102, 0), (256, 1, 128, 0, 102, 0)]
     try:
-        for tj in (64, 128, 256):
-            for ipt in (1, 2, 4):
-                for wg in (128, 256):
-                    for split in (1, 5):
-                        ctx.set_tile(prec, tile_j=tj, ipt=ipt, wg=wg, split=split)
-                        r1 = ctx.force(X, V, X, V, M, eps, prec=prec, i_self=S)
-                        r2 = ctx.force(X, V, X, V, M, eps, prec=prec, i_self=S)
-                        torch.cuda.synchronize()
-                        for u, w in zip(r1, r2):
-                            assert torch.equal(u, w), (tj, ipt, wg, split)
-                        check(tuple(host(t) for t in r1), ref, prec, f"tj={tj} ipt={ipt} wg={wg} S={split}")
+        for tj, ipt, wg, js, unr, wpe in shapes:
+            for split in (1, 5):
+                ctx.set_tile(prec, tile_j=tj, ipt=ipt, wg=wg, split=split, jsrc=js, unroll=unr, waves=wpe)
+                r1 = ctx.force(X, V, X, V, M, eps, prec=prec, i_self=S)
+                r2 = ctx.force(X, V, X, V, M, eps, prec=prec, i_self=S)
+                torch.cuda.synchronize()
+                for u, w in zip(r1, r2):
+                    assert torch.equal(u, w), (tj, ipt, wg, js, unr, wpe, split)
+                check(tuple(host(t) for t in r1), ref, prec,
+                      f"tj={tj} ipt={ipt} wg={wg} js={js} unr={unr} wpe={wpe} S={split}")
     finally:
         ctx.set_tile(prec)
 
