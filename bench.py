@@ -195,6 +195,60 @@ def batched_timing(ctx, prec, steps=32):
             "per_cluster_Gint_s": round(tot / t_per / 1e9, 1)}
 
 
+def block_run(n, t_end, precs, report_every=0.0):
+    """Hermite block steps on the Salpeter workload (Plummer positions and
+    velocities, Salpeter masses 0.1-100 normalised to 1, eps = 1e-3,
+    Aarseth eta = 0.02, levels 2^-3 .. 2^-20) from t = 0 to t_end, both
+    precisions; prints one JSON line."""
+    import torch
+    import nbody_inputs as ics
+    import paper_0707_0438_amd as nb
+    p = ics.plummer(n, ics.seed_for(1), "salpeter")
+    X = torch.from_numpy(p.pos).to("cuda")
+    V = torch.from_numpy(p.vel).to("cuda")
+    M = torch.from_numpy(p.mass).to("cuda")
+    ctx = nb.Context(0)
+    T = int(round(t_end * (1 << 20)))
+    out = {"workload": f"salpeter_block: N={n} Plummer, Salpeter masses [0.1, 100] (sum 1), eps=1e-3, "
+                       f"eta=0.02, block levels 2^-3..2^-20, t = 0 -> {t_end}",
+           "runs": {}}
+    for prec in precs:
+        h = ctx.hermite(n, eps=1e-3, eta=0.02, eta_start=0.01, dt_min_log2=-20, dt_max_log2=-3, prec=prec)
+        h.set_state(X, V, M)
+        ek0, ep0 = h.energy()
+        e0 = ek0 + ep0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        chunk = max(1, int(round((report_every or t_end) * (1 << 20))))
+        target = 0
+        marks = []
+        while target < T:
+            target = min(T, target + chunk)
+            st = h.advance(target)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            marks.append({"t": st["t_ticks"] / (1 << 20), "steps": st["steps"], "sum_active": st["sum_active"],
+                          "wall_s": round(el, 3)})
+            log(f"[block] {prec} t={st['t_ticks'] / (1 << 20):.5f} steps={st['steps']} "
+                f"sum_active={st['sum_active']} wall={el:.1f}s")
+        wall = time.perf_counter() - t0
+        ek, ep = h.energy()
+        e1 = ek + ep
+        inter = float(st["sum_active"]) * n
+        out["runs"][prec] = {
+            "wall_s": round(wall, 3), "block_steps": st["steps"], "sum_active": st["sum_active"],
+            "mean_active": round(st["sum_active"] / max(st["steps"], 1), 2),
+            "Gint_s": round(inter / wall / 1e9, 3), "t_end": st["t_ticks"] / (1 << 20),
+            "E0": e0, "E1": e1, "dE_over_E": (e1 - e0) / e0,
+            "drift_per_time_unit": abs((e1 - e0) / e0) / max(st["t_ticks"] / (1 << 20), 1e-30),
+            "us_per_block_step": round(wall / max(st["steps"], 1) * 1e6, 2),
+            "marks": marks,
+        }
+        h.close()
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
 def copy_calibration(nbytes=1 << 30, reps=4):
     """A plain device-to-device copy of `nbytes` (read nbytes + write nbytes
     per launch), to scale the HBM counters of the force kernel."""
@@ -224,9 +278,16 @@ def main():
                     help="seconds of oracle work for the CPU baseline (0: skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (HBM counter calibration)")
+    ap.add_argument("--block-run", action="store_true",
+                    help="only run the Salpeter block-step workload (--n, --t-end) and print its JSON")
+    ap.add_argument("--t-end", type=float, default=1.0)
+    ap.add_argument("--report-every", type=float, default=0.0)
     args = ap.parse_args()
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.block_run:
+        block_run(args.n if args.n != (1 << 20) else 65536, args.t_end, ["fp32", "ds"], args.report_every)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
