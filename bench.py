@@ -281,6 +281,8 @@ def main():
     ap.add_argument("--block-run", action="store_true",
                     help="only run the Salpeter block-step workload (--n, --t-end) and print its JSON")
     ap.add_argument("--t-end", type=float, default=1.0)
+    ap.add_argument("--extras", default="batched,adjoint",
+                    help="comma list of extra measurements (batched, adjoint) or 'none'")
     ap.add_argument("--report-every", type=float, default=0.0)
     args = ap.parse_args()
     if args.copy_calibration:
@@ -374,10 +376,13 @@ def main():
             "kernel_ms": round(o["kms"] / max(o["launches"], 1), 3),
             "pct_fp32_peak": round(100.0 * FLOPS_PER_INTERACTION * ov * 1e9 / (FP32_PEAK_TFLOPS * 1e12), 2),
         }
-    log("[bench] batched clusters")
-    line["batched"] = batched_timing(ctx, args.prec)
-    log("[bench] adjoint/forward timing")
-    line["adjoint"] = adjoint_timing(nb, ctx, args.prec)
+    extras = [] if args.extras == "none" else args.extras.split(",")
+    if "batched" in extras:
+        log("[bench] batched clusters")
+        line["batched"] = batched_timing(ctx, args.prec)
+    if "adjoint" in extras:
+        log("[bench] adjoint/forward timing")
+        line["adjoint"] = adjoint_timing(nb, ctx, args.prec)
     if args.cpu_budget > 0:
         log("[bench] cpu baseline (oracle)")
         line["cpu_baseline"] = cpu_baseline(p, eps, args.cpu_budget)

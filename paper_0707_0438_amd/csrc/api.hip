@@ -156,7 +156,9 @@ static int choose_split(int64_t ni, int64_t nj, const nbody_tile& t) {
     const int64_t target = 2048;
     if (nblk <= 0 || nblk >= target / 2) return 1;
     int64_t S = (target + nblk - 1) / nblk;
-    const int64_t smax = std::max<int64_t>(1, nj / (2 * (int64_t)t.tile_j));
+    // at least 8 tiles per j-range, so that a work-group's loop amortises its
+    // set-up and the float64 reduce stays small
+    const int64_t smax = std::max<int64_t>(1, nj / (8 * (int64_t)t.tile_j));
     S = std::min(S, smax);
     return (int)std::max<int64_t>(1, S);
 }
@@ -480,9 +482,9 @@ int nbody_select_active(nbody_ctx* c, hipStream_t st, int64_t n, const int64_t* 
         return NBODY_OK;
     }
     DeviceGuard g(c->device);
-    int rc = dev_alloc(c, c->sel, 2 * sizeof(int64_t));
+    int rc = dev_alloc(c, c->sel, (2 + (size_t)select_scratch_words((int)n)) * sizeof(int64_t));
     if (rc) return rc;
-    hipError_t e = launch_select((int)n, t, dt, idx, (int64_t*)c->sel.p, st);
+    hipError_t e = launch_select((int)n, t, dt, idx, (int64_t*)c->sel.p, (int64_t*)c->sel.p + 2, st);
     if (e != hipSuccess) return hip_err(c, e, "select launch");
     int64_t h[2];
     e = hipMemcpyAsync(h, c->sel.p, sizeof h, hipMemcpyDeviceToHost, st);
@@ -613,7 +615,9 @@ static int hermite_step_impl(nbody_hermite* h, hipStream_t st, int64_t t_limit, 
                              int64_t* t_ticks, bool* stopped) {
     nbody_ctx* c = h->ctx;
     const int n = (int)h->n;
-    hipError_t e = launch_select(n, h->t, h->dt, h->idx, h->sel2, st);
+    int rc0 = dev_alloc(c, c->sel, (2 + (size_t)select_scratch_words(n)) * sizeof(int64_t));
+    if (rc0) return rc0;
+    hipError_t e = launch_select(n, h->t, h->dt, h->idx, h->sel2, (int64_t*)c->sel.p + 2, st);
     if (e != hipSuccess) return hip_err(c, e, "select launch");
     int64_t hs[2];
     e = hipMemcpyAsync(hs, h->sel2, sizeof hs, hipMemcpyDeviceToHost, st);

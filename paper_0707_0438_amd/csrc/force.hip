@@ -296,37 +296,37 @@ __global__ __launch_bounds__(WG) void force_batched_kernel(ForceArgs a, BatchArg
 }
 
 // Float64 reduction of split partials in fixed order s = 0 .. S-1, then the
-// self-potential removal and the factor G.
+// self-potential removal and the factor G; one thread per (quantity, i).
 __global__ __launch_bounds__(256) void reduce_kernel(ReduceArgs a) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= a.ni) return;
-    double v[7];
-#pragma unroll
-    for (int q = 0; q < 7; ++q) {
-        double s = 0.0;
-        for (int sp = 0; sp < a.S; ++sp) {
-            const float2 p = a.part[((size_t)sp * 7 + q) * a.ni + i];
-            s += (double)p.x;
-            s += (double)p.y;
-        }
-        v[q] = s;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 7 * (int64_t)a.ni) return;
+    const int q = (int)(t / a.ni);
+    const int i = (int)(t - (int64_t)q * a.ni);
+    double s = 0.0;
+    for (int sp = 0; sp < a.S; ++sp) {
+        const float2 p = a.part[((size_t)sp * 7 + q) * a.ni + i];
+        s += (double)p.x;
+        s += (double)p.y;
+    }
+    if (q < 6) {
+        a.out[q][i] = a.G * s;
+        return;
     }
     if (!a.eps0) {
         const int self = self_index(a.self_mode, a.iidx, a.iself, i);
         if (self >= 0 && self < a.nj) {
             const int R = a.prec == 0 ? kRecFP32 : kRecDS;
             const float ms = a.jpack[(size_t)self * R].w;
-            v[6] -= (double)(ms * __builtin_amdgcn_rsqf(a.eps2));
+            s -= (double)(ms * __builtin_amdgcn_rsqf(a.eps2));
         }
     }
-#pragma unroll
-    for (int q = 0; q < 6; ++q) a.out[q][i] = a.G * v[q];
-    a.out[6][i] = -a.G * v[6];
+    a.out[6][i] = -a.G * s;
 }
 
 hipError_t launch_reduce(const ReduceArgs& a, hipStream_t st) {
     if (a.ni <= 0) return hipSuccess;
-    hipLaunchKernelGGL(reduce_kernel, dim3((a.ni + 255) / 256), dim3(256), 0, st, a);
+    const int64_t n = 7 * (int64_t)a.ni;
+    hipLaunchKernelGGL(reduce_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a);
     return hipGetLastError();
 }
 

@@ -78,9 +78,127 @@ __global__ __launch_bounds__(kSelThreads) void select_kernel(int n, const int64_
     }
 }
 
+// Larger sets: three passes over chunks of kSelChunk consecutive entries
+// (one work-group each): group minima; the global minimum (every group
+// reduces all group minima) and each group's count; then each group's
+// offset (sum of the counts before it) and an ordered compaction.
+constexpr int kSelChunk = 4096;
+constexpr int kSelWG = 256;
+constexpr int kSelPer = kSelChunk / kSelWG;   // consecutive entries per lane
+
+__device__ __forceinline__ int64_t block_min_i64(int64_t m, int64_t* red) {
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    for (int off = 32; off > 0; off >>= 1) {
+        const int64_t o = __shfl_xor(m, off);
+        m = o < m ? o : m;
+    }
+    if (lane == 0) red[w] = m;
+    __syncthreads();
+    int64_t r = red[0];
+    for (int k = 1; k < kSelWG / 64; ++k) r = red[k] < r ? red[k] : r;
+    __syncthreads();
+    return r;
+}
+
+__device__ __forceinline__ int64_t block_sum_i64(int64_t v, int64_t* red) {
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    if (lane == 0) red[w] = v;
+    __syncthreads();
+    int64_t r = 0;
+    for (int k = 0; k < kSelWG / 64; ++k) r += red[k];
+    __syncthreads();
+    return r;
+}
+
+__global__ __launch_bounds__(kSelWG) void select_min_kernel(int n, const int64_t* __restrict__ t,
+                                                            const int64_t* __restrict__ dt,
+                                                            int64_t* __restrict__ gmin) {
+    __shared__ int64_t red[kSelWG / 64];
+    const int base = blockIdx.x * kSelChunk;
+    const int end = min(n, base + kSelChunk);
+    int64_t m = INT64_MAX;
+    for (int k = base + threadIdx.x; k < end; k += kSelWG) {
+        const int64_t v = t[k] + dt[k];
+        m = v < m ? v : m;
+    }
+    m = block_min_i64(m, red);
+    if (threadIdx.x == 0) gmin[blockIdx.x] = m;
+}
+
+__global__ __launch_bounds__(kSelWG) void select_count_kernel(int n, int G, const int64_t* __restrict__ t,
+                                                              const int64_t* __restrict__ dt,
+                                                              const int64_t* __restrict__ gmin,
+                                                              int64_t* __restrict__ gcnt,
+                                                              int64_t* __restrict__ out2) {
+    __shared__ int64_t red[kSelWG / 64];
+    int64_t m = INT64_MAX;
+    for (int g = threadIdx.x; g < G; g += kSelWG) m = gmin[g] < m ? gmin[g] : m;
+    const int64_t tn = block_min_i64(m, red);
+    const int base = blockIdx.x * kSelChunk;
+    const int end = min(n, base + kSelChunk);
+    int64_t c = 0;
+    for (int k = base + threadIdx.x; k < end; k += kSelWG) c += (t[k] + dt[k] == tn) ? 1 : 0;
+    c = block_sum_i64(c, red);
+    if (threadIdx.x == 0) {
+        gcnt[blockIdx.x] = c;
+        if (blockIdx.x == 0) out2[1] = tn;
+    }
+}
+
+__global__ __launch_bounds__(kSelWG) void select_write_kernel(int n, int G, const int64_t* __restrict__ t,
+                                                              const int64_t* __restrict__ dt,
+                                                              const int64_t* __restrict__ gcnt,
+                                                              int64_t* __restrict__ out2,
+                                                              int32_t* __restrict__ idx) {
+    __shared__ int64_t red[kSelWG / 64];
+    __shared__ int wsum[kSelWG / 64];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int64_t tn = out2[1];
+    int64_t before = 0, total = 0;
+    for (int g = tid; g < G; g += kSelWG) {
+        total += gcnt[g];
+        before += g < (int)blockIdx.x ? gcnt[g] : 0;
+    }
+    before = block_sum_i64(before, red);
+    total = block_sum_i64(total, red);
+    const int k0 = blockIdx.x * kSelChunk + tid * kSelPer;
+    int cnt = 0;
+    for (int u = 0; u < kSelPer; ++u) {
+        const int k = k0 + u;
+        cnt += (k < n && t[k] + dt[k] == tn) ? 1 : 0;
+    }
+    int incl = cnt;
+    for (int off = 1; off < 64; off <<= 1) {
+        const int o = __shfl_up(incl, off);
+        if (lane >= off) incl += o;
+    }
+    if (lane == 63) wsum[w] = incl;
+    __syncthreads();
+    int wbase = 0;
+    for (int k = 0; k < w; ++k) wbase += wsum[k];
+    int64_t pos = before + wbase + incl - cnt;
+    for (int u = 0; u < kSelPer; ++u) {
+        const int k = k0 + u;
+        if (k < n && t[k] + dt[k] == tn) idx[pos++] = k;
+    }
+    if (blockIdx.x == 0 && tid == 0) out2[0] = total;
+}
+
+int select_scratch_words(int n) { return n > kSelChunk ? 2 * ((n + kSelChunk - 1) / kSelChunk) : 0; }
+
 hipError_t launch_select(int n, const int64_t* t, const int64_t* dt, int32_t* idx, int64_t* out2,
-                         hipStream_t st) {
-    hipLaunchKernelGGL(select_kernel, dim3(1), dim3(kSelThreads), 0, st, n, t, dt, idx, out2);
+                         int64_t* scratch, hipStream_t st) {
+    if (n <= kSelChunk) {
+        hipLaunchKernelGGL(select_kernel, dim3(1), dim3(kSelThreads), 0, st, n, t, dt, idx, out2);
+        return hipGetLastError();
+    }
+    const int G = (n + kSelChunk - 1) / kSelChunk;
+    int64_t* gmin = scratch;
+    int64_t* gcnt = scratch + G;
+    hipLaunchKernelGGL(select_min_kernel, dim3(G), dim3(kSelWG), 0, st, n, t, dt, gmin);
+    hipLaunchKernelGGL(select_count_kernel, dim3(G), dim3(kSelWG), 0, st, n, G, t, dt, gmin, gcnt, out2);
+    hipLaunchKernelGGL(select_write_kernel, dim3(G), dim3(kSelWG), 0, st, n, G, t, dt, gcnt, out2, idx);
     return hipGetLastError();
 }
 

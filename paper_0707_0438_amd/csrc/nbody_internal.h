@@ -94,9 +94,11 @@ struct PackArgs {
 };
 hipError_t launch_pack(const PackArgs& a, hipStream_t st);
 
-// Active-block selection: out2[0] = n_act, out2[1] = t_next.
+// Active-block selection: out2[0] = n_act, out2[1] = t_next.  scratch: device
+// int64 words, at least select_scratch_words(n).
+int select_scratch_words(int n);
 hipError_t launch_select(int n, const int64_t* t, const int64_t* dt, int32_t* idx, int64_t* out2,
-                         hipStream_t st);
+                         int64_t* scratch, hipStream_t st);
 
 struct CorrectArgs {
     int n_act;
