@@ -156,9 +156,9 @@ static int choose_split(int64_t ni, int64_t nj, const nbody_tile& t) {
     const int64_t target = 2048;
     if (nblk <= 0 || nblk >= target / 2) return 1;
     int64_t S = (target + nblk - 1) / nblk;
-    // at least 8 tiles per j-range, so that a work-group's loop amortises its
+    // at least 4 tiles per j-range, so that a work-group's loop amortises its
     // set-up and the float64 reduce stays small
-    const int64_t smax = std::max<int64_t>(1, nj / (8 * (int64_t)t.tile_j));
+    const int64_t smax = std::max<int64_t>(1, nj / (4 * (int64_t)t.tile_j));
     S = std::min(S, smax);
     return (int)std::max<int64_t>(1, S);
 }
@@ -171,7 +171,7 @@ static nbody_tile default_tile(int prec, int64_t ni, int64_t nj) {
     nbody_tile t;
     const bool large = (double)ni * (double)nj >= 4294967296.0;
     t.tile_j = large ? 256 : 64;
-    t.wg = 256;
+    t.wg = large ? 256 : 128;
     t.ipt = 1;
     t.split = 0;
     t.jsrc = 0;
@@ -665,10 +665,9 @@ static int hermite_step_impl(nbody_hermite* h, hipStream_t st, int64_t t_limit, 
     ca.lmin = h->o.dt_min_log2;
     ca.lmax = h->o.dt_max_log2;
     ca.shared = h->o.shared_dt_log2 != 0;
+    ca.tnow = h->tnow;
     e = launch_correct(ca, st);
     if (e != hipSuccess) return hip_err(c, e, "corrector launch");
-    e = hipMemcpyAsync(h->tnow, h->sel2 + 1, sizeof(int64_t), hipMemcpyDeviceToDevice, st);
-    if (e != hipSuccess) return hip_err(c, e, "block time copy");
     h->t_ticks = tn;
     h->steps += 1;
     h->sum_active += na;

@@ -295,8 +295,23 @@ __global__ __launch_bounds__(WG) void force_batched_kernel(ForceArgs a, BatchArg
     }
 }
 
-// Float64 reduction of split partials in fixed order s = 0 .. S-1, then the
-// self-potential removal and the factor G; one thread per (quantity, i).
+// Float64 reduction of split partials in a fixed order, then the
+// self-potential removal and the factor G.  Few ranges: one thread per
+// (quantity, i) sums s = 0 .. S-1 in order.  Many ranges: one wave per
+// (quantity, i); lane l sums s = l, l + 64, ... in order, then a fixed
+// butterfly over the 64 lane sums.  Either way the result depends only on S.
+__device__ __forceinline__ double reduce_finish(const ReduceArgs& a, int q, int i, double s) {
+    if (q == 6 && !a.eps0) {
+        const int self = self_index(a.self_mode, a.iidx, a.iself, i);
+        if (self >= 0 && self < a.nj) {
+            const int R = a.prec == 0 ? kRecFP32 : kRecDS;
+            const float ms = a.jpack[(size_t)self * R].w;
+            s -= (double)(ms * __builtin_amdgcn_rsqf(a.eps2));
+        }
+    }
+    return q < 6 ? a.G * s : -a.G * s;
+}
+
 __global__ __launch_bounds__(256) void reduce_kernel(ReduceArgs a) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= 7 * (int64_t)a.ni) return;
@@ -308,25 +323,33 @@ __global__ __launch_bounds__(256) void reduce_kernel(ReduceArgs a) {
         s += (double)p.x;
         s += (double)p.y;
     }
-    if (q < 6) {
-        a.out[q][i] = a.G * s;
-        return;
+    a.out[q][i] = reduce_finish(a, q, i, s);
+}
+
+__global__ __launch_bounds__(256) void reduce_wave_kernel(ReduceArgs a) {
+    const int64_t w = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
+    if (w >= 7 * (int64_t)a.ni) return;   // whole waves leave together
+    const int q = (int)(w / a.ni);
+    const int i = (int)(w - (int64_t)q * a.ni);
+    double s = 0.0;
+    for (int sp = lane; sp < a.S; sp += 64) {
+        const float2 p = a.part[((size_t)sp * 7 + q) * a.ni + i];
+        s += (double)p.x;
+        s += (double)p.y;
     }
-    if (!a.eps0) {
-        const int self = self_index(a.self_mode, a.iidx, a.iself, i);
-        if (self >= 0 && self < a.nj) {
-            const int R = a.prec == 0 ? kRecFP32 : kRecDS;
-            const float ms = a.jpack[(size_t)self * R].w;
-            s -= (double)(ms * __builtin_amdgcn_rsqf(a.eps2));
-        }
-    }
-    a.out[6][i] = -a.G * s;
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+    if (lane == 0) a.out[q][i] = reduce_finish(a, q, i, s);
 }
 
 hipError_t launch_reduce(const ReduceArgs& a, hipStream_t st) {
     if (a.ni <= 0) return hipSuccess;
     const int64_t n = 7 * (int64_t)a.ni;
-    hipLaunchKernelGGL(reduce_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a);
+    if (a.S >= 32) {
+        hipLaunchKernelGGL(reduce_wave_kernel, dim3((unsigned)((n * 64 + 255) / 256)), dim3(256), 0, st, a);
+    } else {
+        hipLaunchKernelGGL(reduce_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a);
+    }
     return hipGetLastError();
 }
 

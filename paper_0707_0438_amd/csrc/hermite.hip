@@ -216,6 +216,7 @@ __global__ __launch_bounds__(256) void correct_kernel(CorrectArgs a) {
     if (c >= a.n_act) return;
     const int i = a.idx[c];
     const int64_t tn = *a.tnext;
+    if (c == 0 && a.tnow) *a.tnow = tn;
     const double D = (double)a.dt[i] * kTick;
     double* X[3] = {a.x, a.y, a.z};
     double* V[3] = {a.vx, a.vy, a.vz};

@@ -110,6 +110,7 @@ struct CorrectArgs {
     const double* f[6];               // new a (3) and jerk (3) of the block, [n_act]
     double eta;
     int lmin, lmax, shared;           // shared != 0: keep dt
+    int64_t* tnow;                    // receives the block time (written by one thread; may be NULL)
 };
 hipError_t launch_correct(const CorrectArgs& a, hipStream_t st);
 

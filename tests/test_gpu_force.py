@@ -161,3 +161,22 @@ def test_plummer1m_sampled(ctx):
         got = (host(a)[:, sel], host(j)[:, sel], host(pt)[sel])
         out[prec] = check(got, ref, prec, "N=2^20 sampled")
     assert out["ds"]["acc"]["p99"] < out["fp32"]["acc"]["p99"]
+
+
+@pytest.mark.parametrize("prec", ["ds", "fp32"])
+def test_small_blocks_many_splits(ctx, prec):
+    """Small i-lists against a large, ragged j set: many j-ranges, so the
+    partials go through the wave-per-row float64 reduce."""
+    import torch
+    p = ics.plummer(70001, 107)
+    eps = 1e-3
+    X, V, M = dev(p.pos), dev(p.vel), dev(p.mass)
+    for ni in (1, 7, 100, 1000):
+        sel = np.sort(np.random.default_rng(ni).choice(p.n, ni, replace=False))
+        tile = ctx.get_tile(ni, p.n, prec)
+        assert tile["split"] >= 32 or ni == 1000, tile
+        ref = oracle.force(p.pos[:, sel], p.vel[:, sel], p.pos, p.vel, p.mass, eps, iself=sel)
+        a, j, pt = ctx.force(X[:, sel].contiguous(), V[:, sel].contiguous(), X, V, M, eps, prec=prec,
+                             i_self=dev(sel.astype(np.int32)))
+        torch.cuda.synchronize()
+        check((host(a), host(j), host(pt)), ref, prec, f"ni={ni} split={tile['split']}")
