@@ -65,6 +65,7 @@ struct nbody_hermite {
     int64_t* sel2 = nullptr;  // device [2]: n_act, t_next
     int64_t* tnow = nullptr;  // device scalar: latest block time
     double* e2 = nullptr;     // device [2]
+    DevPlan* plan = nullptr;  // device block-step plan and statistics
     int64_t t_ticks = 0;
     int64_t steps = 0, sum_active = 0;
     void* block = nullptr;    // single allocation holding everything above
@@ -148,19 +149,11 @@ static bool valid_tile(const nbody_tile& t) {
            force_variant_exists(1, t.ipt, t.tile_j, t.wg, t.jsrc, t.unroll, t.waves, false);
 }
 
-// Number of j-ranges for an i-list of ni against nj: enough work-groups to
-// cover the 256 CUs several times, but at least two tiles per range.
+// Number of j-ranges for an i-list of ni against nj (see split_plan).
 static int choose_split(int64_t ni, int64_t nj, const nbody_tile& t) {
-    const int64_t per_blk = (int64_t)t.wg * t.ipt;
-    const int64_t nblk = (ni + per_blk - 1) / per_blk;
-    const int64_t target = 2048;
-    if (nblk <= 0 || nblk >= target / 2) return 1;
-    int64_t S = (target + nblk - 1) / nblk;
-    // at least 4 tiles per j-range, so that a work-group's loop amortises its
-    // set-up and the float64 reduce stays small
-    const int64_t smax = std::max<int64_t>(1, nj / (4 * (int64_t)t.tile_j));
-    S = std::min(S, smax);
-    return (int)std::max<int64_t>(1, S);
+    int nb, S, jc;
+    split_plan(ni, nj, t.wg * t.ipt, t.tile_j, 0, &nb, &S, &jc);
+    return S;
 }
 
 // Default launch shape when neither an override nor a tuned entry exists:
@@ -210,12 +203,8 @@ static int run_force(nbody_ctx* c, hipStream_t st, int prec, double G, double ep
         unr = 0;
         wpe = 0;
     }
-    const int64_t per_blk = (int64_t)wg * ipt;
-    const int nb = (int)((ni + per_blk - 1) / per_blk);
-    int64_t jchunk = (nj + t.split - 1) / t.split;
-    jchunk = ((jchunk + tj - 1) / tj) * tj;
-    if (jchunk <= 0) jchunk = tj;
-    const int S = (int)std::max<int64_t>(1, (nj + jchunk - 1) / jchunk);
+    int nb, S, jchunk;
+    split_plan(ni, nj, wg * ipt, tj, t.split, &nb, &S, &jchunk);
 
     ForceArgs a{};
     a.ipack = ipack;
@@ -520,7 +509,8 @@ int nbody_hermite_create(nbody_ctx* c, nbody_hermite** hp, int64_t n, const nbod
     h->o = *o;
     const size_t nn = (size_t)n;
     const size_t bytes = sizeof(double) * nn * (13 + 1 + 7 + 6) + sizeof(int64_t) * nn * 2 +
-                         sizeof(int32_t) * nn + sizeof(int64_t) * 8 + sizeof(double) * 2 + 4096;
+                         sizeof(int32_t) * nn + sizeof(int64_t) * 8 + sizeof(double) * 2 + sizeof(DevPlan) +
+                         8192;
     ++c->alloc_count;
     if (c->fail_alloc_at > 0 && c->alloc_count == c->fail_alloc_at) {
         delete h;
@@ -547,6 +537,7 @@ int nbody_hermite_create(nbody_ctx* c, nbody_hermite** hp, int64_t n, const nbod
     h->sel2 = (int64_t*)take(sizeof(int64_t) * 2);
     h->tnow = (int64_t*)take(sizeof(int64_t));
     h->e2 = (double*)take(sizeof(double) * 2);
+    h->plan = (DevPlan*)take(sizeof(DevPlan));
     *hp = h;
     return NBODY_OK;
 }
@@ -611,27 +602,36 @@ int nbody_hermite_set_state(nbody_hermite* h, hipStream_t st, nbody_src P) {
     return NBODY_OK;
 }
 
-static int hermite_step_impl(nbody_hermite* h, hipStream_t st, int64_t t_limit, int64_t* n_active,
-                             int64_t* t_ticks, bool* stopped) {
-    nbody_ctx* c = h->ctx;
-    const int n = (int)h->n;
-    int rc0 = dev_alloc(c, c->sel, (2 + (size_t)select_scratch_words(n)) * sizeof(int64_t));
-    if (rc0) return rc0;
-    hipError_t e = launch_select(n, h->t, h->dt, h->idx, h->sel2, (int64_t*)c->sel.p + 2, st);
-    if (e != hipSuccess) return hip_err(c, e, "select launch");
-    int64_t hs[2];
-    e = hipMemcpyAsync(hs, h->sel2, sizeof hs, hipMemcpyDeviceToHost, st);
+// Shape of the plan-driven pairwise launch used for block steps (blocks are
+// usually small; the device decides the split from the block size).
+constexpr int kBlkTile = 64, kBlkWG = 128, kBlkIPT = 1, kBlkGrid = 2048;
+
+static int plan_reset(nbody_hermite* h, hipStream_t st, int64_t t_limit) {
+    DevPlan p{};
+    p.steps = h->steps;
+    p.sum_active = h->sum_active;
+    p.t_last = h->t_ticks;
+    p.t_limit = t_limit;
+    hipError_t e = hipMemcpyAsync(h->plan, &p, sizeof p, hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
-    if (e != hipSuccess) return hip_err(c, e, "block size readback");
-    const int64_t na = hs[0], tn = hs[1];
-    if (stopped) *stopped = false;
-    if (tn > t_limit || na <= 0) {
-        if (stopped) *stopped = true;
-        if (n_active) *n_active = 0;
-        if (t_ticks) *t_ticks = h->t_ticks;
-        return NBODY_OK;
-    }
+    if (e != hipSuccess) return hip_err(h->ctx, e, "plan write");
+    return NBODY_OK;
+}
+
+static int plan_read(nbody_hermite* h, hipStream_t st, DevPlan* p) {
+    hipError_t e = hipMemcpyAsync(p, h->plan, sizeof *p, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_err(h->ctx, e, "plan read");
+    h->steps = p->steps;
+    h->sum_active = p->sum_active;
+    h->t_ticks = p->t_last;
+    return NBODY_OK;
+}
+
+static int pack_predicted(nbody_hermite* h, hipStream_t st, const int64_t* gate) {
+    nbody_ctx* c = h->ctx;
     const int p = (int)h->o.prec;
+    const int n = (int)h->n;
     int rc = dev_alloc(c, c->jpack, sizeof(float4) * rec_words(p) * (size_t)n);
     if (rc) return rc;
     PackArgs pa{};
@@ -645,13 +645,15 @@ static int hermite_step_impl(nbody_hermite* h, hipStream_t st, int64_t t_limit, 
     pa.t = h->t;
     pa.tnext = h->sel2 + 1;
     pa.out = (float4*)c->jpack.p;
-    e = launch_pack(pa, st);
+    pa.gate = gate;
+    hipError_t e = launch_pack(pa, st);
     if (e != hipSuccess) return hip_err(c, e, "predict/pack launch");
-    rc = run_force(c, st, p, h->o.G, h->o.eps, na, (const float4*)c->jpack.p, h->idx, nullptr, 1, n,
-                   (const float4*)c->jpack.p, h->f, nullptr);
-    if (rc) return rc;
+    return NBODY_OK;
+}
+
+static CorrectArgs correct_args(nbody_hermite* h, int n_act, const int64_t* nact_dev) {
     CorrectArgs ca{};
-    ca.n_act = (int)na;
+    ca.n_act = n_act;
     ca.idx = h->idx;
     ca.tnext = h->sel2 + 1;
     ca.x = h->s[0]; ca.y = h->s[1]; ca.z = h->s[2];
@@ -666,13 +668,119 @@ static int hermite_step_impl(nbody_hermite* h, hipStream_t st, int64_t t_limit, 
     ca.lmax = h->o.dt_max_log2;
     ca.shared = h->o.shared_dt_log2 != 0;
     ca.tnow = h->tnow;
-    e = launch_correct(ca, st);
+    ca.nact_dev = nact_dev;
+    return ca;
+}
+
+// Shared steps: every particle is due every step, so the block (all n, in
+// order) and its time are known on the host; no readback.
+static int hermite_step_shared(nbody_hermite* h, hipStream_t st, int64_t t_limit, bool* stopped) {
+    nbody_ctx* c = h->ctx;
+    const int n = (int)h->n;
+    const int64_t tn = h->t_ticks + ((int64_t)1 << (h->o.shared_dt_log2 + 20));
+    *stopped = tn > t_limit;
+    if (*stopped) return NBODY_OK;
+    int rc = dev_alloc(c, c->sel, (2 + (size_t)select_scratch_words(n)) * sizeof(int64_t));
+    if (rc) return rc;
+    hipError_t e = launch_select(n, h->t, h->dt, h->idx, h->sel2, (int64_t*)c->sel.p + 2, st);
+    if (e != hipSuccess) return hip_err(c, e, "select launch");
+    rc = pack_predicted(h, st, nullptr);
+    if (rc) return rc;
+    const int p = (int)h->o.prec;
+    rc = run_force(c, st, p, h->o.G, h->o.eps, n, (const float4*)c->jpack.p, h->idx, nullptr, 1, n,
+                   (const float4*)c->jpack.p, h->f, nullptr);
+    if (rc) return rc;
+    e = launch_correct(correct_args(h, n, nullptr), st);
     if (e != hipSuccess) return hip_err(c, e, "corrector launch");
     h->t_ticks = tn;
     h->steps += 1;
-    h->sum_active += na;
-    if (n_active) *n_active = na;
-    if (t_ticks) *t_ticks = tn;
+    h->sum_active += n;
+    return NBODY_OK;
+}
+
+// Block steps: select, plan, predict/pack, force, reduce, correct, all
+// driven by the device plan (block size, split, end-time gate); a step past
+// the gate leaves every state untouched.  No host synchronisation.
+static int hermite_enqueue_block(nbody_hermite* h, hipStream_t st) {
+    nbody_ctx* c = h->ctx;
+    const int n = (int)h->n;
+    const int p = (int)h->o.prec;
+    hipError_t e = launch_select(n, h->t, h->dt, h->idx, h->sel2, (int64_t*)c->sel.p + 2, st);
+    if (e == hipSuccess) e = launch_plan(h->plan, h->sel2, kBlkWG * kBlkIPT, kBlkTile, n, st);
+    if (e != hipSuccess) return hip_err(c, e, "select/plan launch");
+    int rc = pack_predicted(h, st, &h->plan->n_act);
+    if (rc) return rc;
+    ForceArgs a{};
+    a.ipack = (const float4*)c->jpack.p;
+    a.iidx = h->idx;
+    a.ni = n;
+    a.jpack = (const float4*)c->jpack.p;
+    a.nj = n;
+    a.jchunk = n;
+    a.eps2 = (float)(h->o.eps * h->o.eps);
+    a.G = h->o.G;
+    a.self_mode = 1;
+    for (int q = 0; q < 7; ++q) a.out[q] = h->f[q];
+    a.part = (float2*)c->part.p;
+    a.plan = h->plan;
+    const bool eps0 = h->o.eps == 0.0;
+    e = launch_force_plan(p, kBlkIPT, kBlkTile, kBlkWG, eps0, kBlkGrid, a, st);
+    if (e != hipSuccess) return hip_err(c, e, "force launch");
+    ReduceArgs r{};
+    r.ni = n;
+    r.nj = n;
+    r.prec = p;
+    r.eps0 = eps0 ? 1 : 0;
+    r.part = a.part;
+    r.jpack = a.jpack;
+    r.iidx = h->idx;
+    r.self_mode = 1;
+    r.eps2 = a.eps2;
+    r.G = h->o.G;
+    for (int q = 0; q < 7; ++q) r.out[q] = h->f[q];
+    r.plan = h->plan;
+    e = launch_reduce_plan(r, 1024, st);
+    if (e != hipSuccess) return hip_err(c, e, "reduce launch");
+    e = launch_correct(correct_args(h, n, &h->plan->n_act), st);
+    if (e != hipSuccess) return hip_err(c, e, "corrector launch");
+    return NBODY_OK;
+}
+
+static int block_buffers(nbody_hermite* h) {
+    nbody_ctx* c = h->ctx;
+    const int64_t n = h->n;
+    int rc = dev_alloc(c, c->sel, (2 + (size_t)select_scratch_words((int)n)) * sizeof(int64_t));
+    // partials: S * n_act <= (2048 + nb) * per_blk <= 2049 * per_blk + n
+    if (!rc) rc = dev_alloc(c, c->part, sizeof(float2) * 7 * ((size_t)2049 * kBlkWG * kBlkIPT + (size_t)n));
+    if (!rc) rc = dev_alloc(c, c->jpack, sizeof(float4) * rec_words((int)h->o.prec) * (size_t)n);
+    return rc;
+}
+
+// Run block steps until the next block time would pass t_limit (or, with
+// max_steps > 0, at most that many steps); chunks of steps are enqueued
+// with one readback each.
+static int hermite_block_run(nbody_hermite* h, hipStream_t st, int64_t t_limit, int64_t max_steps,
+                             int64_t* last_nact) {
+    int rc = block_buffers(h);
+    if (!rc) rc = plan_reset(h, st, t_limit);
+    if (rc) return rc;
+    int64_t done = 0;
+    int chunk = 1;
+    for (;;) {
+        int k = chunk;
+        if (max_steps > 0) k = (int)std::min<int64_t>(k, max_steps - done);
+        for (int s = 0; s < k; ++s) {
+            rc = hermite_enqueue_block(h, st);
+            if (rc) return rc;
+        }
+        done += k;
+        DevPlan p;
+        rc = plan_read(h, st, &p);
+        if (rc) return rc;
+        if (last_nact) *last_nact = p.frozen ? 0 : p.n_act;
+        if (p.frozen || (max_steps > 0 && done >= max_steps)) break;
+        chunk = std::min(chunk * 2, 64);
+    }
     return NBODY_OK;
 }
 
@@ -680,18 +788,36 @@ int nbody_hermite_step(nbody_hermite* h, hipStream_t st, int64_t* n_active, int6
     if (!h) return NBODY_ERR_ARG;
     if (!h->has_state) return set_err(h->ctx, NBODY_ERR_STATE, "hermite: set_state or load first");
     DeviceGuard g(h->ctx->device);
-    return hermite_step_impl(h, st, INT64_MAX, n_active, t_ticks, nullptr);
+    if (h->o.shared_dt_log2 != 0) {
+        bool stopped = false;
+        int rc = hermite_step_shared(h, st, INT64_MAX, &stopped);
+        if (rc) return rc;
+        if (n_active) *n_active = h->n;
+        if (t_ticks) *t_ticks = h->t_ticks;
+        return NBODY_OK;
+    }
+    int64_t na = 0;
+    int rc = hermite_block_run(h, st, INT64_MAX, 1, &na);
+    if (rc) return rc;
+    if (n_active) *n_active = na;
+    if (t_ticks) *t_ticks = h->t_ticks;
+    return NBODY_OK;
 }
 
 int nbody_hermite_advance(nbody_hermite* h, hipStream_t st, int64_t t_end, nbody_hermite_stats* stats) {
     if (!h) return NBODY_ERR_ARG;
     if (!h->has_state) return set_err(h->ctx, NBODY_ERR_STATE, "hermite: set_state or load first");
     DeviceGuard g(h->ctx->device);
-    for (;;) {
-        bool stopped = false;
-        int rc = hermite_step_impl(h, st, t_end, nullptr, nullptr, &stopped);
+    if (h->o.shared_dt_log2 != 0) {
+        for (;;) {
+            bool stopped = false;
+            int rc = hermite_step_shared(h, st, t_end, &stopped);
+            if (rc) return rc;
+            if (stopped) break;
+        }
+    } else {
+        int rc = hermite_block_run(h, st, t_end, 0, nullptr);
         if (rc) return rc;
-        if (stopped) break;
     }
     if (stats) {
         stats->steps = h->steps;

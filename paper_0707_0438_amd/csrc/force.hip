@@ -259,6 +259,28 @@ void force_kernel(ForceArgs a) {
         a, sh, blockIdx.x * (WG * IPT), a.ni, jb, je, a.eps2, blockIdx.y);
 }
 
+// Plan-driven launch for block steps: the block size and the split come
+// from the device plan; a fixed grid strides over the nb x S (i-block,
+// j-range) pairs.  Each pair runs exactly the code of force_kernel.
+template <int PREC, int IPT, int TJ, int WG, bool EPS0>
+__global__ __launch_bounds__(WG) void force_kernel_plan(ForceArgs a) {
+    __shared__ float4 sh[2][TJ * Rec<PREC>::R];
+    const DevPlan* pl = a.plan;
+    const int n = (int)pl->n_act;
+    if (n <= 0) return;
+    const int nb = pl->nb, S = pl->S;
+    ForceArgs b = a;
+    b.ni = n;
+    b.jchunk = pl->jchunk;
+    b.partial = S > 1 ? 1 : 0;
+    for (int v = blockIdx.x; v < nb * S; v += gridDim.x) {
+        const int ib = v % nb, s = v / nb;
+        const int jb = s * b.jchunk;
+        const int je = min(b.nj, jb + b.jchunk);
+        force_block<PREC, IPT, TJ, WG, EPS0>(b, sh, ib * (WG * IPT), n, jb, je, b.eps2, s);
+    }
+}
+
 // Same work with the j records read through the scalar data cache instead of
 // LDS (every lane of a wave needs the same j record, so one wave-uniform load
 // serves the wave).  TJ only sets the compensated-fold interval.
@@ -342,6 +364,61 @@ __global__ __launch_bounds__(256) void reduce_wave_kernel(ReduceArgs a) {
     if (lane == 0) a.out[q][i] = reduce_finish(a, q, i, s);
 }
 
+// Plan-driven reduce: grid-stride over (quantity, i) rows, one wave each.
+__global__ __launch_bounds__(256) void reduce_plan_kernel(ReduceArgs a) {
+    const DevPlan* pl = a.plan;
+    const int n = (int)pl->n_act, S = pl->S;
+    if (n <= 0 || S <= 1) return;
+    ReduceArgs b = a;
+    b.ni = n;
+    b.S = S;
+    const int lane = threadIdx.x & 63;
+    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t w = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; w < 7 * (int64_t)n; w += nw) {
+        const int q = (int)(w / n);
+        const int i = (int)(w - (int64_t)q * n);
+        double s = 0.0;
+        for (int sp = lane; sp < S; sp += 64) {
+            const float2 p = b.part[((size_t)sp * 7 + q) * n + i];
+            s += (double)p.x;
+            s += (double)p.y;
+        }
+        for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+        if (lane == 0) b.out[q][i] = reduce_finish(b, q, i, s);
+    }
+}
+
+hipError_t launch_reduce_plan(const ReduceArgs& a, int grid, hipStream_t st) {
+    hipLaunchKernelGGL(reduce_plan_kernel, dim3(grid), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+// One thread turns the selected block (sel2 = n_act, t_next) into the launch
+// geometry and applies the end-time gate of the current advance.
+__global__ void plan_kernel(DevPlan* p, const int64_t* __restrict__ sel2, int per_blk, int tile_j, int nj) {
+    const int64_t n = sel2[0], tn = sel2[1];
+    if (n <= 0 || tn > p->t_limit) {
+        p->n_act = 0;
+        p->frozen = 1;
+        return;
+    }
+    int nb, S, jc;
+    split_plan(n, nj, per_blk, tile_j, 0, &nb, &S, &jc);
+    p->n_act = n;
+    p->t_next = tn;
+    p->nb = nb;
+    p->S = S;
+    p->jchunk = jc;
+    p->steps += 1;
+    p->sum_active += n;
+    p->t_last = tn;
+}
+
+hipError_t launch_plan(DevPlan* p, const int64_t* sel2, int per_blk, int tile_j, int nj, hipStream_t st) {
+    hipLaunchKernelGGL(plan_kernel, dim3(1), dim3(1), 0, st, p, sel2, per_blk, tile_j, nj);
+    return hipGetLastError();
+}
+
 hipError_t launch_reduce(const ReduceArgs& a, hipStream_t st) {
     if (a.ni <= 0) return hipSuccess;
     const int64_t n = 7 * (int64_t)a.ni;
@@ -357,6 +434,7 @@ template <int PREC>
 __global__ __launch_bounds__(256) void pack_kernel(PackArgs a) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= a.n) return;
+    if (a.gate && *a.gate == 0) return;
     double px = a.x[k], py = a.y[k], pz = a.z[k];
     double qx = a.vx[k], qy = a.vy[k], qz = a.vz[k];
     if (a.t) {
@@ -567,6 +645,25 @@ hipError_t launch_force_batched(int prec, int ipt, int tj, int wg, int grid, con
 }
 
 int force_variant_count() { return (int)(sizeof(kVariants) / sizeof(kVariants[0])); }
+
+// plan-driven shapes (block steps)
+bool force_plan_variant_exists(int prec, int ipt, int tj, int wg) {
+    return (prec == 0 || prec == 1) && ipt == 1 && tj == 64 && wg == 128;
+}
+
+hipError_t launch_force_plan(int prec, int ipt, int tj, int wg, bool eps0, int grid, const ForceArgs& a,
+                             hipStream_t st) {
+    if (!force_plan_variant_exists(prec, ipt, tj, wg)) return hipErrorInvalidValue;
+    if (prec == 0 && !eps0)
+        hipLaunchKernelGGL((force_kernel_plan<0, 1, 64, 128, false>), dim3(grid), dim3(128), 0, st, a);
+    else if (prec == 0)
+        hipLaunchKernelGGL((force_kernel_plan<0, 1, 64, 128, true>), dim3(grid), dim3(128), 0, st, a);
+    else if (!eps0)
+        hipLaunchKernelGGL((force_kernel_plan<1, 1, 64, 128, false>), dim3(grid), dim3(128), 0, st, a);
+    else
+        hipLaunchKernelGGL((force_kernel_plan<1, 1, 64, 128, true>), dim3(grid), dim3(128), 0, st, a);
+    return hipGetLastError();
+}
 
 bool force_variant_at(int k, int* prec, int* ipt, int* tj, int* wg, int* jsrc, int* unr, int* wpe, bool* eps0) {
     if (k < 0 || k >= force_variant_count()) return false;

@@ -211,9 +211,20 @@ __device__ __forceinline__ double norm3(double a, double b, double c) { return s
 //   x1 = x_p + a2 D^4/24 + a3 D^5/120,  v1 = v_p + a2 D^3/6 + a3 D^4/24,
 // then the Aarseth criterion with a2 carried to the new time, and the
 // power-of-two level rule.
+__device__ __forceinline__ void correct_one(const CorrectArgs& a, int c);
+
 __global__ __launch_bounds__(256) void correct_kernel(CorrectArgs a) {
+    if (a.nact_dev) {
+        const int n = (int)*a.nact_dev;
+        for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x) correct_one(a, c);
+        return;
+    }
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= a.n_act) return;
+    correct_one(a, c);
+}
+
+__device__ __forceinline__ void correct_one(const CorrectArgs& a, int c) {
     const int i = a.idx[c];
     const int64_t tn = *a.tnext;
     if (c == 0 && a.tnow) *a.tnow = tn;
@@ -253,7 +264,10 @@ __global__ __launch_bounds__(256) void correct_kernel(CorrectArgs a) {
 
 hipError_t launch_correct(const CorrectArgs& a, hipStream_t st) {
     if (a.n_act <= 0) return hipSuccess;
-    hipLaunchKernelGGL(correct_kernel, dim3((a.n_act + 255) / 256), dim3(256), 0, st, a);
+    // plan-driven: n_act is an upper bound (grid-stride up to the device count)
+    const int grid = a.nact_dev ? (a.n_act + 255) / 256 < 1024 ? (a.n_act + 255) / 256 : 1024
+                                : (a.n_act + 255) / 256;
+    hipLaunchKernelGGL(correct_kernel, dim3(grid), dim3(256), 0, st, a);
     return hipGetLastError();
 }
 

@@ -20,6 +20,47 @@ constexpr int kRecFP32 = 2;
 constexpr int kRecDS = 3;
 inline int rec_words(int prec) { return prec == 0 ? kRecFP32 : kRecDS; }
 
+// Launch geometry of the pairwise kernel for an i-list of ni against nj:
+// nb i-blocks of per_blk particles and S j-ranges of jchunk records (a
+// multiple of the tile).  Enough work-groups to cover the 256 CUs several
+// times, with at least 4 tiles per j-range.  Used by the host for direct
+// calls and by the device for block steps whose size only it knows.
+__host__ __device__ inline void split_plan(int64_t ni, int64_t nj, int per_blk, int tile_j, int split_req,
+                                           int* nb_out, int* S_out, int* jchunk_out) {
+    const int64_t nb = (ni + per_blk - 1) / per_blk;
+    int64_t S = split_req;
+    if (S <= 0) {
+        const int64_t target = 2048;
+        if (nb <= 0 || nb >= target / 2) {
+            S = 1;
+        } else {
+            S = (target + nb - 1) / nb;
+            int64_t smax = nj / (4 * (int64_t)tile_j);
+            if (smax < 1) smax = 1;
+            if (S > smax) S = smax;
+            if (S < 1) S = 1;
+        }
+    }
+    int64_t jchunk = (nj + S - 1) / S;
+    jchunk = ((jchunk + tile_j - 1) / tile_j) * tile_j;
+    if (jchunk <= 0) jchunk = tile_j;
+    int64_t S2 = (nj + jchunk - 1) / jchunk;
+    if (S2 < 1) S2 = 1;
+    *nb_out = (int)nb;
+    *S_out = (int)S2;
+    *jchunk_out = (int)jchunk;
+}
+
+// Block-step state the device keeps between launches (one per driver).
+struct DevPlan {
+    int64_t n_act;              // block size after the end-time gate (0: nothing to do)
+    int64_t t_next;
+    int64_t steps, sum_active;  // running statistics
+    int64_t t_last;             // latest block time taken
+    int64_t t_limit;            // end time of the current advance (ticks)
+    int nb, S, jchunk, frozen;  // launch geometry; frozen = the gate stopped a step
+};
+
 // Arguments of the pairwise kernel (passed by value).
 struct ForceArgs {
     const float4* ipack;    // i records
@@ -35,6 +76,7 @@ struct ForceArgs {
     int self_mode;          // 0: iself[i], 1: iidx[i], 2: i itself
     double* out[7];         // ax ay az jx jy jz pot (final mode)
     float2* part;           // [S][7][ni] (hi, lo) partials (partial mode)
+    const DevPlan* plan;    // plan-driven launch: ni, S, jchunk come from here
 };
 
 struct ReduceArgs {
@@ -47,6 +89,7 @@ struct ReduceArgs {
     float eps2;
     double G;
     double* out[7];
+    const DevPlan* plan;    // plan-driven launch: ni and S come from here
 };
 
 // Launch the pairwise kernel for one configuration; returns hipError_t.
@@ -58,6 +101,12 @@ bool force_variant_exists(int prec, int ipt, int tile_j, int wg, int jsrc, int u
 int force_variant_count();
 bool force_variant_at(int k, int* prec, int* ipt, int* tj, int* wg, int* jsrc, int* unr, int* wpe, bool* eps0);
 hipError_t launch_reduce(const ReduceArgs& a, hipStream_t st);
+// Plan-driven launches (block sizes known only on the device).
+bool force_plan_variant_exists(int prec, int ipt, int tile_j, int wg);
+hipError_t launch_force_plan(int prec, int ipt, int tile_j, int wg, bool eps0, int grid, const ForceArgs& a,
+                             hipStream_t st);
+hipError_t launch_reduce_plan(const ReduceArgs& a, int grid, hipStream_t st);
+hipError_t launch_plan(DevPlan* p, const int64_t* sel2, int per_blk, int tile_j, int nj, hipStream_t st);
 
 // ---- batched clusters ----
 struct BatchArgs {
@@ -91,6 +140,7 @@ struct PackArgs {
     const int64_t* t;                              // ticks (or NULL: no prediction)
     const int64_t* tnext;                          // device scalar
     float4* out;
+    const int64_t* gate;                           // device scalar; 0 = skip (or NULL)
 };
 hipError_t launch_pack(const PackArgs& a, hipStream_t st);
 
@@ -111,6 +161,7 @@ struct CorrectArgs {
     double eta;
     int lmin, lmax, shared;           // shared != 0: keep dt
     int64_t* tnow;                    // receives the block time (written by one thread; may be NULL)
+    const int64_t* nact_dev;          // device block size (plan-driven launch) or NULL
 };
 hipError_t launch_correct(const CorrectArgs& a, hipStream_t st);
 

@@ -147,3 +147,43 @@ def test_energy_matches_oracle(ctx):
         rk, rp = oracle.energy(p.pos, p.vel, p.mass, 0.01)
         assert ek == pytest.approx(rk, rel=1e-13)
         assert ep == pytest.approx(rp, rel=1e-6 if prec == "ds" else 1e-4)
+
+
+def test_block_advance_in_pieces_equals_one_advance(ctx):
+    """The device-resident block stepping enqueues steps in chunks; where the
+    chunks and the advance calls fall must not change a single bit."""
+    p = ics.plummer(3000, 203, "salpeter")
+    T = TICKS // 64
+    runs = []
+    for pieces in ((T,), (T // 4, T // 2, T), (T // 8, T // 8, 3 * T // 4, T)):
+        h = ctx.hermite(p.n, eps=1e-3, eta=0.02, prec="ds")
+        h.set_state(dev(p.pos), dev(p.vel), dev(p.mass))
+        for t in pieces:
+            st = h.advance(t)
+        runs.append((st, gpu_state(h)))
+        h.close()
+    for st, s in runs[1:]:
+        assert st == runs[0][0]
+        for k in s:
+            assert np.array_equal(s[k], runs[0][1][k]), k
+    st0 = runs[0][0]
+    assert st0["steps"] > 10 and st0["sum_active"] > st0["steps"]
+
+
+def test_block_steps_unsoftened_kepler(ctx):
+    """Two bodies on an e = 0.5 orbit with eps = 0 in block mode (the
+    zero-softening path): the orbit and its energy against the oracle."""
+    from test_oracle_hermite import kepler_state
+    m = np.array([0.6, 0.4])
+    x0, v0 = kepler_state(0.6, 0.4, 1.0, 0.5, 0.0)
+    ref = oracle.HermiteState(x0, v0, m)
+    oracle.hermite_run(ref, TICKS // 2, eps=0.0, eta=0.01, lmin=-20, lmax=-6, init=True)
+    h = ctx.hermite(2, eps=0.0, eta=0.01, dt_min_log2=-20, dt_max_log2=-6, prec="ds")
+    h.set_state(dev(x0), dev(v0), dev(m))
+    st = h.advance(TICKS // 2)
+    s = gpu_state(h)
+    assert np.all(s["t"] == TICKS // 2) and st["t_ticks"] == TICKS // 2
+    print("kepler block steps gpu", st["steps"], "oracle", ref.steps, "max|dx|", np.abs(s["x"] - ref.x).max(),
+          flush=True)
+    assert np.abs(s["x"] - ref.x).max() < 1e-6
+    assert abs(st["steps"] - ref.steps) <= max(2, ref.steps // 20)
