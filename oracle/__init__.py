@@ -14,6 +14,10 @@ of 2^-20 time units.  Functions and the passages they follow:
 * :func:`predict`, :func:`correct`, :func:`aarseth_dt`, :func:`quantise_dt`,
   :func:`select_active`, :func:`hermite_run` -- the fourth-order Hermite
   scheme with block time steps (Section 3 and 3.1).
+* :func:`force_acc` -- the force-only evaluation (acceleration and
+  potential, no jerk) that Section 4 uses for its treecode runs.
+* :func:`nearest` -- the nearest neighbour of each i (Section 3.3).
+* :func:`leapfrog` -- a kick-drift-kick run on :func:`force_acc`.
 * :func:`energy` -- Eq. 2 (Section 4) energy bookkeeping.
 * :func:`hermite_shared_forward`, :func:`hermite_shared_adjoint` -- shared
   step runs and their gradient with respect to x0, v0, m.
@@ -85,6 +89,10 @@ def _load():
             lib.oracle_hermite_shared_adjoint.argtypes = [I64, P, P, P, D, D, D, I64, P, P,
                                                           P, P, P, I]
             lib.oracle_hermite_shared_adjoint.restype = I
+            lib.oracle_nearest.argtypes = [I64, P, P, I64, P, P, P, I]
+            lib.oracle_nearest.restype = I
+            lib.oracle_leapfrog.argtypes = [I64, P, P, P, D, D, D, I64, P, P, I, I]
+            lib.oracle_leapfrog.restype = I
             lib.oracle_num_threads.argtypes = []
             lib.oracle_num_threads.restype = I
             _lib = lib
@@ -265,3 +273,45 @@ def hermite_shared_adjoint(x0, v0, m, eps, D, nsteps, gx_end, gv_end=None, G=1.0
     if rc != 0:
         raise MemoryError("oracle_hermite_shared_adjoint")
     return gx0, gv0, gm
+
+
+def force_acc(xi, xj, mj, eps, G=1.0, iself=None, nthreads=0):
+    """Acceleration and potential only (the force-only evaluation).  The
+    jerk needs velocities; these two do not, so zero velocities are passed
+    and the jerk is dropped.  Returns (acc (3, ni), pot (ni,))."""
+    xi = _f64(xi)
+    xj = _f64(xj)
+    acc, _, pot = force(xi, np.zeros_like(xi), xj, np.zeros_like(xj), mj, eps, G=G, iself=iself,
+                        nthreads=nthreads)
+    return acc, pot
+
+
+def nearest(xi, xj, iself=None, nthreads=0):
+    """Nearest j of every i by unsoftened distance, self excluded by index,
+    lowest j on ties.  Returns (nn int64 (ni,), r2 (ni,)); -1 / +inf when
+    there is no candidate."""
+    lib = _load()
+    xi = _f64(xi); ni = xi.shape[1]
+    xj = _f64(xj); nj = xj.shape[1]
+    s = None if iself is None else np.ascontiguousarray(iself, dtype=np.int64)
+    nn = np.empty(ni, dtype=np.int64); r2 = np.empty(ni)
+    rc = lib.oracle_nearest(ni, _p(xi), _p(s), nj, _p(xj), _p(nn), _p(r2), nthreads)
+    if rc:
+        raise ValueError(f"oracle_nearest failed ({rc})")
+    return nn, r2
+
+
+def leapfrog(x0, v0, m, eps, dt, nsteps, G=1.0, acc=None, nthreads=0):
+    """Kick-drift-kick run of ``nsteps`` steps of ``dt``; ``acc`` is a(x0)
+    if known.  Returns (x, v, acc, pot) at the end."""
+    lib = _load()
+    x = _f64(x0).copy(); n = x.shape[1]
+    v = _f64(v0, (3, n)).copy(); m = _f64(m, (n,))
+    have = acc is not None
+    a = _f64(acc, (3, n)).copy() if have else np.zeros((3, n))
+    pot = np.empty(n)
+    rc = lib.oracle_leapfrog(n, _p(x), _p(v), _p(m), float(G), float(eps), float(dt), int(nsteps),
+                             _p(a), _p(pot), 1 if have else 0, nthreads)
+    if rc:
+        raise ValueError(f"oracle_leapfrog failed ({rc})")
+    return x, v, a, pot

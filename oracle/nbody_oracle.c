@@ -566,3 +566,87 @@ done:
     free(ga); free(gj); free(tx); free(tv); free(tm); free(self);
     return rc;
 }
+
+/* ------------------------------------------------------------------------
+ * Nearest neighbour (Section 3.3: besides force, jerk and potential the
+ * GRAPE reports, for every i-particle being updated, the particle closest
+ * to it; the GPU finds it with one distance comparison per pair inside the
+ * force loop).
+ *
+ * For each i: nn[i] is the j != iself[i] with the smallest unsoftened
+ * squared distance |x_j - x_i|^2, the lowest such j when several are equally
+ * close; r2[i] is that squared distance.  With no candidate (nj == 0, or
+ * the only j is i itself) nn[i] = -1 and r2[i] = +inf.  Coincident
+ * distinct particles are candidates at distance 0.
+ * ---------------------------------------------------------------------- */
+int oracle_nearest(int64_t ni, const double *xi, const int64_t *iself, int64_t nj, const double *xj,
+                   int64_t *nn, double *r2, int nthreads) {
+    if (ni < 0 || nj < 0) return -1;
+    set_threads(nthreads);
+    int64_t i;
+#pragma omp parallel for schedule(static)
+    for (i = 0; i < ni; ++i) {
+        const double px = xi[i], py = xi[ni + i], pz = xi[2 * ni + i];
+        const int64_t self = iself ? iself[i] : -1;
+        int64_t best = -1;
+        double bd = INFINITY;
+        for (int64_t j = 0; j < nj; ++j) {
+            if (j == self) continue;
+            const double rx = xj[j] - px, ry = xj[nj + j] - py, rz = xj[2 * nj + j] - pz;
+            const double d = rx * rx + ry * ry + rz * rz;
+            if (d < bd) {   /* strict: the first (lowest) j wins a tie */
+                bd = d;
+                best = j;
+            }
+        }
+        nn[i] = best;
+        r2[i] = bd;
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------
+ * Shared-step leapfrog driven by acceleration alone.  Section 4 runs a
+ * Barnes-Hut treecode on the library with the jerk and nearest-neighbour
+ * work switched off, since such integrators need only the acceleration;
+ * the standard second-order kick-drift-kick (velocity Verlet) form of one
+ * step of length dt is
+ *   v_h = v_0 + a_0 dt/2,   x_1 = x_0 + v_h dt,
+ *   a_1 = a(x_1),           v_1 = v_h + a_1 dt/2,
+ * with a(x) the softened acceleration of every particle from all others
+ * (self excluded by index).  acc holds a(x) on entry when have_acc != 0
+ * (else it is computed first) and a(x) at the end on return; pot (may be
+ * NULL) receives the potential at the end.  x, v, acc are 3 x n rows and
+ * are updated in place.
+ * ---------------------------------------------------------------------- */
+int oracle_leapfrog(int64_t n, double *x, double *v, const double *m, double G, double eps, double dt,
+                    int64_t nsteps, double *acc, double *pot, int have_acc, int nthreads) {
+    if (n < 0 || nsteps < 0 || eps < 0) return -1;
+    if (n == 0) return 0;
+    int64_t *self = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+    double *ph = (double *)malloc(sizeof(double) * (size_t)n);
+    if (!self || !ph) {
+        free(self);
+        free(ph);
+        return -2;
+    }
+    for (int64_t i = 0; i < n; ++i) self[i] = i;
+    int rc = 0;
+    if (!have_acc) rc = oracle_force(n, x, v, self, n, x, v, m, G, eps, acc, NULL, ph, nthreads);
+    const double h = 0.5 * dt;
+    for (int64_t s = 0; s < nsteps && rc == 0; ++s) {
+        for (int64_t k = 0; k < 3 * n; ++k) {
+            v[k] += acc[k] * h;
+            x[k] += v[k] * dt;
+        }
+        rc = oracle_force(n, x, v, self, n, x, v, m, G, eps, acc, NULL, ph, nthreads);
+        for (int64_t k = 0; k < 3 * n; ++k) v[k] += acc[k] * h;
+    }
+    if (rc == 0 && pot) {
+        if (nsteps == 0 && have_acc) rc = oracle_force(n, x, v, self, n, x, v, m, G, eps, NULL, NULL, ph, nthreads);
+        memcpy(pot, ph, sizeof(double) * (size_t)n);
+    }
+    free(self);
+    free(ph);
+    return rc;
+}
