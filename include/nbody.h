@@ -171,6 +171,48 @@ int nbody_force(nbody_ctx *ctx, hipStream_t stream, nbody_prec prec, double G, d
                 int64_t n_i, nbody_src I, const int32_t *i_self,
                 int64_t n_j, nbody_src J, nbody_out out);
 
+/* Force-only evaluation: acceleration and potential as in nbody_force,
+ * without the jerk.  Section 4 runs the library under a treecode, which
+ * integrates with the acceleration alone, with the jerk and nearest-neighbour
+ * work switched off (38 instead of 60 conventional flops per interaction,
+ * Table 3).  The velocity rows of I and J are not read and may be NULL;
+ * out.jx, out.jy, out.jz are not written and may be NULL.  Otherwise as
+ * nbody_force (arguments, self handling, errors). */
+int nbody_force_acc(nbody_ctx *ctx, hipStream_t stream, nbody_prec prec, double G, double eps,
+                    int64_t n_i, nbody_src I, const int32_t *i_self,
+                    int64_t n_j, nbody_src J, nbody_out out);
+
+/* nbody_force plus the nearest neighbour of every i (Section 3.3: the GRAPE
+ * hardware reports it alongside force, jerk and potential, and the GPU finds
+ * it with one distance comparison per pair in the force loop).
+ * nn: device int32[n_i], required: the j index with the smallest unsoftened
+ * squared distance |x_j - x_i|^2 among j != i_self[i]; the lowest such j
+ * when several are equally close; -1 if there is no candidate.
+ * nn_r2: device double[n_i] or NULL: that squared distance as the kernel
+ * computed it (float32, from the relative coordinate of the chosen
+ * precision), +inf where nn is -1.  Distances are compared in float32, so
+ * two j whose distances differ by less than float32 rounding may be taken
+ * in either order.  Errors as nbody_force, plus NBODY_ERR_ARG for
+ * nn == NULL with n_i > 0. */
+int nbody_force_nn(nbody_ctx *ctx, hipStream_t stream, nbody_prec prec, double G, double eps,
+                   int64_t n_i, nbody_src I, const int32_t *i_self,
+                   int64_t n_j, nbody_src J, nbody_out out, int32_t *nn, double *nn_r2);
+
+/* Shared-step kick-drift-kick leapfrog of n particles on the force-only
+ * evaluation (the acceleration-only integration of Section 4):
+ *   v += a dt/2;  x += v dt;  a = a(x);  v += a dt/2   (nsteps times),
+ * every particle acting on every other, self excluded.
+ * x, v, acc: device double[3][n] (rows x, y, z), updated in place; acc must
+ * hold a(x) on entry when have_acc != 0, else it is computed first; on
+ * return it holds a(x) at the end, so runs chain without a re-evaluation.
+ * m: device double[n].  pot: device double[n] or NULL: the potential at the
+ * end.  Enqueued on `stream` without host synchronisation.  Returns
+ * NBODY_ERR_ARG for NULL x, v, m or acc with n > 0, misaligned rows,
+ * nsteps < 0, non-finite dt, and as nbody_force for G and eps. */
+int nbody_leapfrog(nbody_ctx *ctx, hipStream_t stream, nbody_prec prec, double G, double eps,
+                   double dt, int nsteps, int64_t n, double *x, double *v, const double *m,
+                   double *acc, double *pot, int have_acc);
+
 /* ---- adjoint of the force ------------------------------------------------- */
 
 /* Vector-Jacobian product of nbody_force (the derivative of the sums of

@@ -34,7 +34,7 @@ EXPORTS = [
     "nbody_hermite_save", "nbody_hermite_load", "nbody_block_level", "nbody_kernel_timing",
     "nbody_kernel_time", "nbody_force_vjp", "nbody_force_vjp_self", "nbody_shared_ckpt_bytes",
     "nbody_shared_run", "nbody_shared_adjoint", "nbody_force_batched", "nbody_batch_hermite",
-    "nbody_autotune_batched",
+    "nbody_autotune_batched", "nbody_force_acc", "nbody_force_nn", "nbody_leapfrog",
 ]
 
 ERRORS = {0: "OK", -1: "NBODY_ERR_ARG", -2: "NBODY_ERR_NOMEM", -3: "NBODY_ERR_DEVICE",
@@ -128,6 +128,9 @@ def lib():
         "nbody_shared_run": ([P, P, I, D, D, D, I, I64, Src, P, P, P, I], I),
         "nbody_shared_adjoint": ([P, P, I, D, D, D, I, I64, Src, P, I, P, P, P, P, P], I),
         "nbody_kernel_time": ([P, C.POINTER(D), C.POINTER(I64)], I),
+        "nbody_force_acc": ([P, P, I, D, D, I64, Src, P, I64, Src, Out], I),
+        "nbody_force_nn": ([P, P, I, D, D, I64, Src, P, I64, Src, Out, P, P], I),
+        "nbody_leapfrog": ([P, P, I, D, D, D, I, I64, P, P, P, P, P, I], I),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -278,6 +281,65 @@ class Context:
         self._check(lib().nbody_force(self._h, _stream(stream), PREC[prec], float(G), float(eps),
                                       ni, I, sp, nj, J, O), "nbody_force")
         return acc, jerk, pot
+
+    def force_acc(self, xi, xj, mj, eps, G=1.0, prec="ds", i_self=None, stream=None):
+        """(acc (3, n_i), pot (n_i,)): the force-only evaluation, see
+        nbody_force_acc.  No velocities are needed."""
+        torch = _torch()
+        ni, nj = xi.shape[1], xj.shape[1]
+        xs, xjs = _rows(xi, ni, "I.x"), _rows(xj, nj, "J.x")
+        I = Src(xs[0], xs[1], xs[2], None, None, None, None)
+        J = Src(xjs[0], xjs[1], xjs[2], None, None, None, _vec(mj, nj, "J.m"))
+        acc = torch.empty((3, ni), dtype=torch.float64, device=xi.device)
+        pot = torch.empty((ni,), dtype=torch.float64, device=xi.device)
+        a = _rows(acc, ni, "acc")
+        O = Out(a[0], a[1], a[2], None, None, None, _vec(pot, ni, "pot"))
+        sp = _vec(i_self, ni, "i_self", torch.int32) if i_self is not None else None
+        self._check(lib().nbody_force_acc(self._h, _stream(stream), PREC[prec], float(G), float(eps),
+                                          ni, I, sp, nj, J, O), "nbody_force_acc")
+        return acc, pot
+
+    def force_nn(self, xi, vi, xj, vj, mj, eps, G=1.0, prec="ds", i_self=None, want_r2=True,
+                 stream=None):
+        """(acc, jerk, pot, nn (n_i,) int32, nn_r2 (n_i,) or None): nbody_force
+        plus the nearest neighbour of each i, see nbody_force_nn."""
+        torch = _torch()
+        ni, nj = xi.shape[1], xj.shape[1]
+        I = _src(xi, vi, None, ni, "I")
+        J = _src(xj, vj, mj, nj, "J")
+        dev = xi.device
+        acc = torch.empty((3, ni), dtype=torch.float64, device=dev)
+        jerk = torch.empty((3, ni), dtype=torch.float64, device=dev)
+        pot = torch.empty((ni,), dtype=torch.float64, device=dev)
+        nn = torch.empty((ni,), dtype=torch.int32, device=dev)
+        r2 = torch.empty((ni,), dtype=torch.float64, device=dev) if want_r2 else None
+        a, j = _rows(acc, ni, "acc"), _rows(jerk, ni, "jerk")
+        O = Out(a[0], a[1], a[2], j[0], j[1], j[2], _vec(pot, ni, "pot"))
+        sp = _vec(i_self, ni, "i_self", torch.int32) if i_self is not None else None
+        self._check(lib().nbody_force_nn(self._h, _stream(stream), PREC[prec], float(G), float(eps),
+                                         ni, I, sp, nj, J, O, nn.data_ptr() if ni else None,
+                                         r2.data_ptr() if r2 is not None and ni else None),
+                    "nbody_force_nn")
+        return acc, jerk, pot, nn, r2
+
+    def leapfrog(self, x, v, m, eps, dt, nsteps, acc=None, G=1.0, prec="ds", want_pot=True,
+                 stream=None):
+        """Kick-drift-kick run in place on x, v ((3, n) float64); ``acc`` is
+        a(x) if known (it is updated in place), else computed first.
+        Returns (acc, pot or None) at the end; see nbody_leapfrog."""
+        torch = _torch()
+        n = x.shape[1]
+        _rows(x, n, "x"); _rows(v, n, "v"); _vec(m, n, "m")
+        have = acc is not None
+        if not have:
+            acc = torch.empty((3, n), dtype=torch.float64, device=x.device)
+        _rows(acc, n, "acc")
+        pot = torch.empty((n,), dtype=torch.float64, device=x.device) if want_pot else None
+        ptr = lambda t: t.data_ptr() if t is not None and n else None
+        self._check(lib().nbody_leapfrog(self._h, _stream(stream), PREC[prec], float(G), float(eps),
+                                         float(dt), int(nsteps), n, ptr(x), ptr(v), ptr(m), ptr(acc),
+                                         ptr(pot), 1 if have else 0), "nbody_leapfrog")
+        return acc, pot
 
     def force_vjp(self, xi, vi, xj, vj, mj, eps, ga, gj=None, gp=None, G=1.0, prec="ds",
                   i_self=None, want=("xi", "vi", "xj", "vj", "mj"), stream=None):

@@ -32,7 +32,7 @@ struct DevBuf {
 struct nbody_ctx {
     int device = -1;          // -1: argument-checking context without a device
     std::string err;
-    DevBuf ipack, jpack, part, sel, scratch64, vrec_i, vrec_j, vpart, integ, hist, bplan, bstate;
+    DevBuf ipack, jpack, part, sel, scratch64, vrec_i, vrec_j, vpart, integ, hist, bplan, bstate, lf;
     // batched Hermite graph (captured on a context-owned stream)
     hipStream_t gstream = nullptr;
     hipEvent_t gev[2] = {nullptr, nullptr};
@@ -124,19 +124,21 @@ static int dev_alloc(nbody_ctx* c, DevBuf& b, size_t bytes) {
 
 static bool aligned8(const void* p) { return ((uintptr_t)p & 7u) == 0; }
 
-static int check_src(nbody_ctx* c, const nbody_src& s, bool need_m, const char* name) {
+static int check_src(nbody_ctx* c, const nbody_src& s, bool need_m, const char* name, bool need_v = true) {
     const double* rows[7] = {s.x, s.y, s.z, s.vx, s.vy, s.vz, s.m};
     for (int k = 0; k < 7; ++k) {
         if (k == 6 && !need_m) continue;
+        if (k >= 3 && k < 6 && !need_v) continue;
         if (!rows[k]) return set_err(c, NBODY_ERR_ARG, "%s: row %d is NULL", name, k);
         if (!aligned8(rows[k])) return set_err(c, NBODY_ERR_ARG, "%s: row %d is not 8-byte aligned", name, k);
     }
     return NBODY_OK;
 }
 
-static int check_out(nbody_ctx* c, const nbody_out& o) {
+static int check_out(nbody_ctx* c, const nbody_out& o, bool need_jerk = true) {
     double* rows[7] = {o.ax, o.ay, o.az, o.jx, o.jy, o.jz, o.pot};
     for (int k = 0; k < 7; ++k) {
+        if (k >= 3 && k < 6 && !need_jerk) continue;
         if (!rows[k]) return set_err(c, NBODY_ERR_ARG, "out: row %d is NULL", k);
         if (!aligned8(rows[k])) return set_err(c, NBODY_ERR_ARG, "out: row %d is not 8-byte aligned", k);
     }
@@ -185,23 +187,36 @@ static nbody_tile pick_tile(nbody_ctx* c, int prec, int64_t ni, int64_t nj) {
     return t;
 }
 
-// Core evaluation: i records (ipack, iidx) against j records (jpack).
+// Core evaluation: i records (ipack, iidx) against j records (jpack).  kind 0
+// writes all 7 rows of out; kind 1 (force only) rows 0-2 and 6; kind 2 all 7
+// plus the nearest neighbour (nn, nn_r2).
 static int run_force(nbody_ctx* c, hipStream_t st, int prec, double G, double eps, int64_t ni,
                      const float4* ipack, const int32_t* iidx, const int32_t* iself, int self_mode,
-                     int64_t nj, const float4* jpack, double* const out[7], const nbody_tile* forced) {
+                     int64_t nj, const float4* jpack, double* const out[7], const nbody_tile* forced,
+                     int kind = 0, int32_t* nn = nullptr, double* nn_r2 = nullptr) {
     if (ni == 0) return NBODY_OK;
     nbody_tile t = forced ? *forced : pick_tile(c, prec, ni, nj);
     if (t.split <= 0) t.split = choose_split(ni, nj, t);
     const bool eps0 = eps == 0.0;
     int ipt = t.ipt, tj = t.tile_j, wg = t.wg, jsrc = t.jsrc, unr = t.unroll, wpe = t.waves;
-    if (!force_variant_exists(prec, ipt, tj, wg, jsrc, unr, wpe, eps0)) {
-        // the unsoftened path exists in one LDS shape per precision
-        ipt = ipt >= 2 ? 2 : 1;
-        tj = 128;
-        wg = 256;
+    if (!force_variant_exists(prec, ipt, tj, wg, jsrc, unr, wpe, eps0, kind)) {
+        if (eps0) {
+            // the unsoftened path exists in few LDS shapes per precision
+            ipt = (kind == 0 && ipt >= 2) ? 2 : 1;
+            tj = 128;
+            wg = 256;
+        } else {
+            // the other kinds fall back to the default shape for the size
+            const nbody_tile d = default_tile(prec, ni, nj);
+            ipt = d.ipt;
+            tj = d.tile_j;
+            wg = d.wg;
+            unr = d.unroll;
+        }
         jsrc = 0;
-        unr = 0;
+        if (eps0) unr = 0;
         wpe = 0;
+        if (!forced) t.split = 0;
     }
     int nb, S, jchunk;
     split_plan(ni, nj, wg * ipt, tj, t.split, &nb, &S, &jchunk);
@@ -218,11 +233,16 @@ static int run_force(nbody_ctx* c, hipStream_t st, int prec, double G, double ep
     a.iself = iself;
     a.self_mode = self_mode;
     for (int q = 0; q < 7; ++q) a.out[q] = out[q];
+    if (kind == 1) a.out[3] = a.out[4] = a.out[5] = nullptr;
+    a.nn = nn;
+    a.nn_r2 = nn_r2;
     a.partial = S > 1 ? 1 : 0;
     if (S > 1) {
-        int rc = dev_alloc(c, c->part, sizeof(float2) * 7 * (size_t)S * (size_t)ni);
+        const size_t rows = kind == 2 ? 8 : 7;
+        int rc = dev_alloc(c, c->part, sizeof(float2) * rows * (size_t)S * (size_t)ni);
         if (rc) return rc;
         a.part = (float2*)c->part.p;
+        if (kind == 2) a.nnpart = a.part + 7 * (size_t)S * (size_t)ni;
     }
     hipEvent_t tb = nullptr, te = nullptr;
     if (c->timing) {
@@ -236,7 +256,7 @@ static int run_force(nbody_ctx* c, hipStream_t st, int prec, double G, double ep
         c->ev_used += 2;
         if (hipEventRecord(tb, st) != hipSuccess) return set_err(c, NBODY_ERR_DEVICE, "event record");
     }
-    hipError_t e = launch_force(prec, ipt, tj, wg, jsrc, unr, wpe, eps0, nb, S, a, st);
+    hipError_t e = launch_force(prec, ipt, tj, wg, jsrc, unr, wpe, eps0, nb, S, a, st, kind);
     if (e != hipSuccess) return hip_err(c, e, "force kernel launch");
     if (te && hipEventRecord(te, st) != hipSuccess) return set_err(c, NBODY_ERR_DEVICE, "event record");
     if (S > 1) {
@@ -253,9 +273,13 @@ static int run_force(nbody_ctx* c, hipStream_t st, int prec, double G, double ep
         r.self_mode = self_mode;
         r.eps2 = a.eps2;
         r.G = G;
-        for (int q = 0; q < 7; ++q) r.out[q] = out[q];
+        for (int q = 0; q < 7; ++q) r.out[q] = a.out[q];
         e = launch_reduce(r, st);
         if (e != hipSuccess) return hip_err(c, e, "split reduce launch");
+        if (kind == 2) {
+            e = launch_nn_reduce((int)ni, S, a.nnpart, nn, nn_r2, st);
+            if (e != hipSuccess) return hip_err(c, e, "nearest-neighbour reduce launch");
+        }
     }
     return NBODY_OK;
 }
@@ -456,6 +480,109 @@ int nbody_force(nbody_ctx* c, hipStream_t st, nbody_prec prec, double G, double 
     double* o[7] = {out.ax, out.ay, out.az, out.jx, out.jy, out.jz, out.pot};
     return run_force(c, st, p, G, eps, n_i, ip, nullptr, i_self, 0, n_j, (const float4*)c->jpack.p, o,
                      nullptr);
+}
+
+// Shared argument checks and packing of nbody_force_acc / nbody_force_nn.
+static int force_kind(nbody_ctx* c, hipStream_t st, nbody_prec prec, double G, double eps, int64_t n_i,
+                      nbody_src I, const int32_t* i_self, int64_t n_j, nbody_src J, nbody_out out, int kind,
+                      int32_t* nn, double* nn_r2) {
+    if (!c) return NBODY_ERR_ARG;
+    if (int rc = check_common(c, prec, G, eps)) return rc;
+    if (n_i < 0 || n_j < 0) return set_err(c, NBODY_ERR_ARG, "n_i and n_j must be >= 0");
+    if (n_i > kMaxN || n_j > kMaxN) return set_err(c, NBODY_ERR_ARG, "n_i and n_j must be <= 2^31-1");
+    const bool vel = kind != 1;
+    if (n_i > 0) {
+        if (int rc = check_src(c, I, false, "I", vel)) return rc;
+        if (int rc = check_out(c, out, vel)) return rc;
+        if (kind == 2 && !nn) return set_err(c, NBODY_ERR_ARG, "nn is NULL");
+        if (kind == 2 && !aligned8(nn_r2)) return set_err(c, NBODY_ERR_ARG, "nn_r2 is not 8-byte aligned");
+    }
+    if (n_j > 0)
+        if (int rc = check_src(c, J, true, "J", vel)) return rc;
+    if (n_i > 0 && n_j == 0 && i_self)
+        return set_err(c, NBODY_ERR_ARG, "i_self given with an empty j set");
+    if (int rc = need_device(c)) return rc;
+    if (n_i == 0) return NBODY_OK;
+    DeviceGuard g(c->device);
+    if (!g.ok) return set_err(c, NBODY_ERR_DEVICE, "hipSetDevice(%d) failed", c->device);
+    if (!vel) {
+        // velocities are not read by the force-only evaluation
+        I.vx = I.vy = I.vz = nullptr;
+        J.vx = J.vy = J.vz = nullptr;
+    }
+    const int p = (int)prec;
+    int rc = pack_rows(c, st, p, n_j, J, true, c->jpack);
+    if (rc) return rc;
+    const float4* ip = (const float4*)c->jpack.p;
+    if (!(n_i == n_j && same_src(I, J))) {
+        rc = pack_rows(c, st, p, n_i, I, false, c->ipack);
+        if (rc) return rc;
+        ip = (const float4*)c->ipack.p;
+    }
+    double* o[7] = {out.ax, out.ay, out.az, vel ? out.jx : nullptr, vel ? out.jy : nullptr,
+                    vel ? out.jz : nullptr, out.pot};
+    return run_force(c, st, p, G, eps, n_i, ip, nullptr, i_self, 0, n_j, (const float4*)c->jpack.p, o, nullptr,
+                     kind, nn, nn_r2);
+}
+
+int nbody_force_acc(nbody_ctx* c, hipStream_t st, nbody_prec prec, double G, double eps, int64_t n_i,
+                    nbody_src I, const int32_t* i_self, int64_t n_j, nbody_src J, nbody_out out) {
+    return force_kind(c, st, prec, G, eps, n_i, I, i_self, n_j, J, out, 1, nullptr, nullptr);
+}
+
+int nbody_force_nn(nbody_ctx* c, hipStream_t st, nbody_prec prec, double G, double eps, int64_t n_i,
+                   nbody_src I, const int32_t* i_self, int64_t n_j, nbody_src J, nbody_out out, int32_t* nn,
+                   double* nn_r2) {
+    return force_kind(c, st, prec, G, eps, n_i, I, i_self, n_j, J, out, 2, nn, nn_r2);
+}
+
+int nbody_leapfrog(nbody_ctx* c, hipStream_t st, nbody_prec prec, double G, double eps, double dt, int nsteps,
+                   int64_t n, double* x, double* v, const double* m, double* acc, double* pot, int have_acc) {
+    if (!c) return NBODY_ERR_ARG;
+    if (int rc = check_common(c, prec, G, eps)) return rc;
+    if (!isfinite(dt)) return set_err(c, NBODY_ERR_ARG, "dt must be finite");
+    if (nsteps < 0) return set_err(c, NBODY_ERR_ARG, "nsteps must be >= 0");
+    if (n < 0 || n > kMaxN) return set_err(c, NBODY_ERR_ARG, "n must be in [0, 2^31-1]");
+    if (n > 0) {
+        const void* need[5] = {x, v, m, acc, pot};
+        const char* names[5] = {"x", "v", "m", "acc", "pot"};
+        for (int k = 0; k < 5; ++k) {
+            if (!need[k] && k < 4) return set_err(c, NBODY_ERR_ARG, "%s is NULL", names[k]);
+            if (!aligned8(need[k])) return set_err(c, NBODY_ERR_ARG, "%s is not 8-byte aligned", names[k]);
+        }
+    }
+    if (int rc = need_device(c)) return rc;
+    if (n == 0) return NBODY_OK;
+    DeviceGuard g(c->device);
+    if (!g.ok) return set_err(c, NBODY_ERR_DEVICE, "hipSetDevice(%d) failed", c->device);
+    const int p = (int)prec;
+    // scratch: a potential row when the caller wants none, and an
+    // acceleration block for a potential-only evaluation
+    int rc = dev_alloc(c, c->lf, sizeof(double) * 4 * (size_t)n);
+    if (rc) return rc;
+    double* pot_s = (double*)c->lf.p;
+    double* acc_s = pot_s + n;
+    rc = dev_alloc(c, c->jpack, sizeof(float4) * rec_words(p) * (size_t)n);
+    if (rc) return rc;
+    const float4* jp = (const float4*)c->jpack.p;
+    double* const prow = pot ? pot : pot_s;
+    auto eval = [&](double* a3) {
+        double* o[7] = {a3, a3 + n, a3 + 2 * n, nullptr, nullptr, nullptr, prow};
+        return run_force(c, st, p, G, eps, n, jp, nullptr, nullptr, 2, n, jp, o, nullptr, 1);
+    };
+    nbody_src P{x, x + n, x + 2 * n, nullptr, nullptr, nullptr, m};
+    if (!have_acc || (nsteps == 0 && pot)) {
+        if ((rc = pack_rows(c, st, p, n, P, true, c->jpack))) return rc;
+        if ((rc = eval(have_acc ? acc_s : acc))) return rc;
+    }
+    for (int s = 0; s < nsteps; ++s) {
+        hipError_t e = launch_lf_kick_drift_pack(p, (int)n, x, v, acc, m, 0.5 * dt, dt, (float4*)c->jpack.p, st);
+        if (e != hipSuccess) return hip_err(c, e, "leapfrog kick-drift launch");
+        if ((rc = eval(acc))) return rc;
+        e = launch_lf_kick((int)n, v, acc, 0.5 * dt, st);
+        if (e != hipSuccess) return hip_err(c, e, "leapfrog kick launch");
+    }
+    return NBODY_OK;
 }
 
 int nbody_select_active(nbody_ctx* c, hipStream_t st, int64_t n, const int64_t* t, const int64_t* dt,
@@ -1609,9 +1736,10 @@ int nbody_autotune(nbody_ctx* c, hipStream_t st, nbody_prec prec, double G, doub
     }
     std::vector<nbody_tile> cand;
     for (int k = 0; k < force_variant_count(); ++k) {
-        int vp, vi, vt, vw, vj, vu, vo;
+        int vp, vi, vt, vw, vj, vu, vo, vk;
         bool ve;
-        if (force_variant_at(k, &vp, &vi, &vt, &vw, &vj, &vu, &vo, &ve) && vp == p && ve == (eps == 0.0))
+        if (force_variant_at(k, &vp, &vi, &vt, &vw, &vj, &vu, &vo, &ve, &vk) && vk == 0 && vp == p &&
+            ve == (eps == 0.0))
             cand.push_back(nbody_tile{vt, vi, vw, 0, vj, vu, vo});
     }
     nbody_tile bt{};

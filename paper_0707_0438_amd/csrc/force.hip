@@ -22,6 +22,13 @@
 //    work-groups that write (hi, lo) partials, reduced afterwards in
 //    float64 in fixed order (the j-split of Section 3.2, with the combine
 //    moved from the host to the device).
+//
+// Kinds of evaluation (compile-time, so the default kernel carries no extra
+// work): KIND 0 acceleration + jerk + potential; KIND 1 acceleration +
+// potential only (the force-only evaluation of Section 4, which a
+// treecode or leapfrog needs); KIND 2 adds to KIND 0 the nearest neighbour
+// of each i (Section 3.3): one unsoftened r^2 per pair, kept when smaller
+// than the best so far and j is not i itself, so the lowest j wins a tie.
 #include "nbody_internal.h"
 
 namespace nb {
@@ -47,7 +54,8 @@ __device__ __forceinline__ void two_sum_fold(float& hi, float& lo, float p) {
 // One work-group's share: i slots ibase + k*WG + tid (k < IPT) below iend,
 // against j in [jb, je).  Results go to the float64 outputs (with the
 // self-potential removal) or to split partial slot `split`.
-template <int PREC, int IPT, int TJ, int WG, bool EPS0, bool JS = false, int UNR = 4, bool PIPE = false>
+template <int PREC, int IPT, int TJ, int WG, bool EPS0, bool JS = false, int UNR = 4, bool PIPE = false,
+          int KIND = 0>
 __device__ __forceinline__ void force_block(const ForceArgs& a, float4 (*sh)[TJ * Rec<PREC>::R], int ibase,
                                             int iend, int jb, int je, float eps2, int split) {
     constexpr int R = Rec<PREC>::R;
@@ -73,6 +81,16 @@ __device__ __forceinline__ void force_block(const ForceArgs& a, float4 (*sh)[TJ 
         ix[k] = r0.x; iy[k] = r0.y; iz[k] = r0.z;
         iu[k] = r1.x; iv[k] = r1.y; iw[k] = r1.z;
         lx[k] = r2.x; ly[k] = r2.y; lz[k] = r2.z;
+    }
+    // nearest-neighbour state (KIND 2): best r^2, its j, and the j index of i
+    float bnr[IPT];
+    int bnj[IPT], selfk[IPT];
+#pragma unroll
+    for (int k = 0; k < IPT; ++k) {
+        const int ii = ibase + k * WG + tid;
+        bnr[k] = __builtin_inff();
+        bnj[k] = -1;
+        selfk[k] = (KIND == 2 && ii < iend) ? self_index(a.self_mode, a.iidx, a.iself, ii) : -1;
     }
 
     float acc[IPT][7];
@@ -111,7 +129,7 @@ __device__ __forceinline__ void force_block(const ForceArgs& a, float4 (*sh)[TJ 
     // the instruction that reads it
     float eps2v;
     asm volatile("v_mov_b32 %0, %1" : "=v"(eps2v) : "s"(eps2));
-    auto interact = [&](const float4& q0, const float4& q1, const float4& q2) {
+    auto interact = [&](const float4& q0, const float4& q1, const float4& q2, int jidx) {
 #pragma unroll
         for (int k = 0; k < IPT; ++k) {
             float dx, dy, dz;
@@ -124,11 +142,29 @@ __device__ __forceinline__ void force_block(const ForceArgs& a, float4 (*sh)[TJ 
                 dy = q0.y - iy[k];
                 dz = q0.z - iz[k];
             }
-            const float ux = q1.x - iu[k], uy = q1.y - iv[k], uz = q1.z - iw[k];
-            const float s = fmaf(dz, dz, fmaf(dy, dy, fmaf(dx, dx, eps2v)));
-            const float rv = fmaf(dz, uz, fmaf(dy, uy, dx * ux));
+            float s;
+            if (KIND == 2) {
+                const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+                s = r2 + eps2v;
+                const bool better = (r2 < bnr[k]) & (jidx != selfk[k]);
+                bnr[k] = better ? r2 : bnr[k];
+                bnj[k] = better ? jidx : bnj[k];
+            } else {
+                s = fmaf(dz, dz, fmaf(dy, dy, fmaf(dx, dx, eps2v)));
+            }
             float rinv = __builtin_amdgcn_rsqf(s);
             if (EPS0) rinv = s > 0.f ? rinv : 0.f;
+            if (KIND == 1) {
+                const float mr = q0.w * rinv;
+                const float mr3 = mr * (rinv * rinv);
+                acc[k][0] = fmaf(mr3, dx, acc[k][0]);
+                acc[k][1] = fmaf(mr3, dy, acc[k][1]);
+                acc[k][2] = fmaf(mr3, dz, acc[k][2]);
+                acc[k][6] += mr;
+                continue;
+            }
+            const float ux = q1.x - iu[k], uy = q1.y - iv[k], uz = q1.z - iw[k];
+            const float rv = fmaf(dz, uz, fmaf(dy, uy, dx * ux));
             const float rinv2 = rinv * rinv;
             const float mr = q0.w * rinv;
             const float mr3 = mr * rinv2;
@@ -166,7 +202,7 @@ __device__ __forceinline__ void force_block(const ForceArgs& a, float4 (*sh)[TJ 
                 const float4 q1 = jp[(size_t)j * R + 1];
                 float4 q2 = make_float4(0.f, 0.f, 0.f, 0.f);
                 if (PREC == 1) q2 = jp[(size_t)j * R + 2];
-                interact(q0, q1, q2);
+                interact(q0, q1, q2, j);
             }
             fold();
         }
@@ -181,6 +217,7 @@ __device__ __forceinline__ void force_block(const ForceArgs& a, float4 (*sh)[TJ 
             const int buf = t & 1;
             if (t + 1 < ntiles) load_tile(t + 1);
             const float4* tile = sh[buf];
+            const int jt = jb + t * TJ;
             if (PIPE) {
                 // software pipeline: the record of j+1 is read from LDS while
                 // j is being computed
@@ -194,7 +231,7 @@ __device__ __forceinline__ void force_block(const ForceArgs& a, float4 (*sh)[TJ 
                     const float4 n1 = tile[jn * R + 1];
                     float4 n2 = make_float4(0.f, 0.f, 0.f, 0.f);
                     if (PREC == 1) n2 = tile[jn * R + 2];
-                    interact(q0, q1, q2);
+                    interact(q0, q1, q2, jt + jj);
                     q0 = n0;
                     q1 = n1;
                     q2 = n2;
@@ -206,7 +243,7 @@ __device__ __forceinline__ void force_block(const ForceArgs& a, float4 (*sh)[TJ 
                     const float4 q1 = tile[jj * R + 1];
                     float4 q2 = make_float4(0.f, 0.f, 0.f, 0.f);
                     if (PREC == 1) q2 = tile[jj * R + 2];
-                    interact(q0, q1, q2);
+                    interact(q0, q1, q2, jt + jj);
                 }
             }
             fold();
@@ -226,10 +263,18 @@ __device__ __forceinline__ void force_block(const ForceArgs& a, float4 (*sh)[TJ 
             hi[q] = PREC == 1 ? chi[k][q] : acc[k][q];
             lo[q] = PREC == 1 ? clo[k][q] : 0.f;
         }
+        int nnj = bnj[k];
+        float nnr = bnr[k];
+        if (nnj >= je) {   // a padding record: this range held no candidate
+            nnj = -1;
+            nnr = __builtin_inff();
+        }
         if (a.partial) {
             const size_t base = (size_t)split * 7 * a.ni + ii;
 #pragma unroll
-            for (int q = 0; q < 7; ++q) a.part[base + (size_t)q * a.ni] = make_float2(hi[q], lo[q]);
+            for (int q = 0; q < 7; ++q)
+                if (KIND != 1 || q < 3 || q == 6) a.part[base + (size_t)q * a.ni] = make_float2(hi[q], lo[q]);
+            if (KIND == 2) a.nnpart[(size_t)split * a.ni + ii] = make_float2(nnr, __int_as_float(nnj));
         } else {
             double pot = (double)hi[6] + (double)lo[6];
             if (!EPS0) {
@@ -241,8 +286,13 @@ __device__ __forceinline__ void force_block(const ForceArgs& a, float4 (*sh)[TJ 
                 }
             }
 #pragma unroll
-            for (int q = 0; q < 6; ++q) a.out[q][ii] = a.G * ((double)hi[q] + (double)lo[q]);
+            for (int q = 0; q < 6; ++q)
+                if (KIND != 1 || q < 3) a.out[q][ii] = a.G * ((double)hi[q] + (double)lo[q]);
             a.out[6][ii] = -a.G * pot;
+            if (KIND == 2) {
+                a.nn[ii] = nnj;
+                if (a.nn_r2) a.nn_r2[ii] = nnj >= 0 ? (double)nnr : (double)__builtin_inff();
+            }
         }
     }
 }
@@ -256,6 +306,16 @@ void force_kernel(ForceArgs a) {
     const int jb = blockIdx.y * a.jchunk;
     const int je = min(a.nj, jb + a.jchunk);
     force_block<PREC, IPT, TJ, WG, EPS0, false, (UNR >= 100 ? UNR - 100 : UNR), (UNR >= 100)>(
+        a, sh, blockIdx.x * (WG * IPT), a.ni, jb, je, a.eps2, blockIdx.y);
+}
+
+// The force-only (KIND 1) and nearest-neighbour (KIND 2) evaluations.
+template <int PREC, int KIND, int IPT, int TJ, int WG, bool EPS0, int UNR>
+__global__ __launch_bounds__(WG) void force_kernel_kind(ForceArgs a) {
+    __shared__ float4 sh[2][TJ * Rec<PREC>::R];
+    const int jb = blockIdx.y * a.jchunk;
+    const int je = min(a.nj, jb + a.jchunk);
+    force_block<PREC, IPT, TJ, WG, EPS0, false, (UNR >= 100 ? UNR - 100 : UNR), (UNR >= 100), KIND>(
         a, sh, blockIdx.x * (WG * IPT), a.ni, jb, je, a.eps2, blockIdx.y);
 }
 
@@ -339,6 +399,7 @@ __global__ __launch_bounds__(256) void reduce_kernel(ReduceArgs a) {
     if (t >= 7 * (int64_t)a.ni) return;
     const int q = (int)(t / a.ni);
     const int i = (int)(t - (int64_t)q * a.ni);
+    if (!a.out[q]) return;   // a row the evaluation does not produce
     double s = 0.0;
     for (int sp = 0; sp < a.S; ++sp) {
         const float2 p = a.part[((size_t)sp * 7 + q) * a.ni + i];
@@ -354,6 +415,7 @@ __global__ __launch_bounds__(256) void reduce_wave_kernel(ReduceArgs a) {
     if (w >= 7 * (int64_t)a.ni) return;   // whole waves leave together
     const int q = (int)(w / a.ni);
     const int i = (int)(w - (int64_t)q * a.ni);
+    if (!a.out[q]) return;   // the whole wave shares q
     double s = 0.0;
     for (int sp = lane; sp < a.S; sp += 64) {
         const float2 p = a.part[((size_t)sp * 7 + q) * a.ni + i];
@@ -419,6 +481,32 @@ hipError_t launch_plan(DevPlan* p, const int64_t* sel2, int per_blk, int tile_j,
     return hipGetLastError();
 }
 
+// Nearest neighbour over the j-ranges: the smallest r^2, the lower range
+// (hence the lower j) on ties.
+__global__ __launch_bounds__(256) void nn_reduce_kernel(int ni, int S, const float2* __restrict__ nnpart,
+                                                        int32_t* __restrict__ nn, double* __restrict__ nn_r2) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ni) return;
+    float best = __builtin_inff();
+    int bj = -1;
+    for (int sp = 0; sp < S; ++sp) {
+        const float2 p = nnpart[(size_t)sp * ni + i];
+        const int j = __float_as_int(p.y);
+        if (j >= 0 && (bj < 0 || p.x < best)) {
+            best = p.x;
+            bj = j;
+        }
+    }
+    nn[i] = bj;
+    if (nn_r2) nn_r2[i] = bj >= 0 ? (double)best : (double)__builtin_inff();
+}
+
+hipError_t launch_nn_reduce(int ni, int S, const float2* nnpart, int32_t* nn, double* nn_r2, hipStream_t st) {
+    if (ni <= 0) return hipSuccess;
+    hipLaunchKernelGGL(nn_reduce_kernel, dim3((ni + 255) / 256), dim3(256), 0, st, ni, S, nnpart, nn, nn_r2);
+    return hipGetLastError();
+}
+
 hipError_t launch_reduce(const ReduceArgs& a, hipStream_t st) {
     if (a.ni <= 0) return hipSuccess;
     const int64_t n = 7 * (int64_t)a.ni;
@@ -436,7 +524,7 @@ __global__ __launch_bounds__(256) void pack_kernel(PackArgs a) {
     if (k >= a.n) return;
     if (a.gate && *a.gate == 0) return;
     double px = a.x[k], py = a.y[k], pz = a.z[k];
-    double qx = a.vx[k], qy = a.vy[k], qz = a.vz[k];
+    double qx = a.vx ? a.vx[k] : 0.0, qy = a.vy ? a.vy[k] : 0.0, qz = a.vz ? a.vz[k] : 0.0;
     if (a.t) {
         const double D = (double)(*a.tnext - a.t[k]) * kTick;
         predict1(px, qx, a.ax[k], a.jx[k], D, px, qx);
@@ -570,6 +658,12 @@ static hipError_t launch_one_js(int nb, int S, const ForceArgs& a, hipStream_t s
     return hipGetLastError();
 }
 
+template <int PREC, int KIND, int IPT, int TJ, int WG, bool EPS0, int UNR>
+static hipError_t launch_kind(int nb, int S, const ForceArgs& a, hipStream_t st) {
+    hipLaunchKernelGGL((force_kernel_kind<PREC, KIND, IPT, TJ, WG, EPS0, UNR>), dim3(nb, S), dim3(WG), 0, st, a);
+    return hipGetLastError();
+}
+
 template <int PREC, int IPT, int TJ, int WG, bool EPS0>
 static hipError_t launch_batched_one(int grid, const ForceArgs& a, const BatchArgs& b, hipStream_t st) {
     if (EPS0) return hipErrorInvalidValue;
@@ -583,14 +677,22 @@ typedef hipError_t (*BatchedFn)(int, const ForceArgs&, const BatchArgs&, hipStre
 struct Variant {
     int prec, ipt, tj, wg, jsrc, unr, wpe;
     bool eps0;
+    int kind;
     LaunchFn fn;
     BatchedFn bfn;
 };
 
 #define NB_V(P, I, T, W, E) \
-    {P, I, T, W, 0, 4, 0, E, &launch_one<P, I, T, W, E, 4, 0>, &launch_batched_one<P, I, T, W, E>}
-#define NB_X(P, I, T, W, U, O) {P, I, T, W, 0, U, O, false, &launch_one<P, I, T, W, false, U, O>, nullptr}
-#define NB_J(P, I, W) {P, I, 128, W, 1, 4, 0, false, &launch_one_js<P, I, 128, W, false, 4, 0>, nullptr}
+    {P, I, T, W, 0, 4, 0, E, 0, &launch_one<P, I, T, W, E, 4, 0>, &launch_batched_one<P, I, T, W, E>}
+#define NB_X(P, I, T, W, U, O) {P, I, T, W, 0, U, O, false, 0, &launch_one<P, I, T, W, false, U, O>, nullptr}
+#define NB_J(P, I, W) {P, I, 128, W, 1, 4, 0, false, 0, &launch_one_js<P, I, 128, W, false, 4, 0>, nullptr}
+#define NB_K(P, K, I, T, W, U, E) {P, I, T, W, 0, U, 0, E, K, &launch_kind<P, K, I, T, W, E, U>, nullptr}
+#define NB_KP(P)                                                                                          \
+    NB_K(P, 1, 1, 64, 128, 4, false), NB_K(P, 1, 1, 128, 256, 4, false), NB_K(P, 1, 2, 128, 256, 4, false), \
+    NB_K(P, 1, 1, 256, 256, 102, false), NB_K(P, 1, 2, 256, 256, 101, false),                              \
+    NB_K(P, 1, 2, 256, 256, 4, false), NB_K(P, 1, 4, 256, 256, 4, false), NB_K(P, 1, 1, 128, 256, 4, true), \
+    NB_K(P, 2, 1, 64, 128, 4, false), NB_K(P, 2, 1, 128, 256, 4, false), NB_K(P, 2, 1, 256, 256, 102, false), \
+    NB_K(P, 2, 2, 256, 256, 101, false), NB_K(P, 2, 1, 128, 256, 4, true)
 #define NB_VT(P, I, W)                                                                  \
     NB_V(P, I, 64, W, false), NB_V(P, I, 128, W, false), NB_V(P, I, 256, W, false)
 #define NB_VW(P, I) NB_VT(P, I, 128), NB_VT(P, I, 256)
@@ -614,25 +716,29 @@ static const Variant kVariants[] = {
     // unsoftened (eps = 0) path: one shape per precision
     NB_V(0, 1, 128, 256, true), NB_V(0, 2, 128, 256, true),
     NB_V(1, 1, 128, 256, true), NB_V(1, 2, 128, 256, true),
+    // force-only (kind 1) and nearest-neighbour (kind 2) evaluations
+    NB_KP(0),
+    NB_KP(1),
 };
 
 // unr / wpe of 0 select the default (unroll 4, no occupancy request)
-static const Variant* find_variant(int prec, int ipt, int tj, int wg, int jsrc, int unr, int wpe, bool eps0) {
+static const Variant* find_variant(int prec, int ipt, int tj, int wg, int jsrc, int unr, int wpe, bool eps0,
+                                   int kind = 0) {
     if (unr == 0) unr = 4;
     for (const Variant& v : kVariants)
         if (v.prec == prec && v.ipt == ipt && v.tj == tj && v.wg == wg && v.jsrc == jsrc && v.unr == unr &&
-            v.wpe == wpe && v.eps0 == eps0)
+            v.wpe == wpe && v.eps0 == eps0 && v.kind == kind)
             return &v;
     return nullptr;
 }
 
-bool force_variant_exists(int prec, int ipt, int tj, int wg, int jsrc, int unr, int wpe, bool eps0) {
-    return find_variant(prec, ipt, tj, wg, jsrc, unr, wpe, eps0) != nullptr;
+bool force_variant_exists(int prec, int ipt, int tj, int wg, int jsrc, int unr, int wpe, bool eps0, int kind) {
+    return find_variant(prec, ipt, tj, wg, jsrc, unr, wpe, eps0, kind) != nullptr;
 }
 
 hipError_t launch_force(int prec, int ipt, int tj, int wg, int jsrc, int unr, int wpe, bool eps0, int nb, int S,
-                        const ForceArgs& a, hipStream_t st) {
-    const Variant* v = find_variant(prec, ipt, tj, wg, jsrc, unr, wpe, eps0);
+                        const ForceArgs& a, hipStream_t st, int kind) {
+    const Variant* v = find_variant(prec, ipt, tj, wg, jsrc, unr, wpe, eps0, kind);
     if (!v) return hipErrorInvalidValue;
     return v->fn(nb, S, a, st);
 }
@@ -665,10 +771,12 @@ hipError_t launch_force_plan(int prec, int ipt, int tj, int wg, bool eps0, int g
     return hipGetLastError();
 }
 
-bool force_variant_at(int k, int* prec, int* ipt, int* tj, int* wg, int* jsrc, int* unr, int* wpe, bool* eps0) {
+bool force_variant_at(int k, int* prec, int* ipt, int* tj, int* wg, int* jsrc, int* unr, int* wpe, bool* eps0,
+                      int* kind) {
     if (k < 0 || k >= force_variant_count()) return false;
     const Variant& v = kVariants[k];
     *prec = v.prec; *ipt = v.ipt; *tj = v.tj; *wg = v.wg; *jsrc = v.jsrc; *unr = v.unr; *wpe = v.wpe; *eps0 = v.eps0;
+    *kind = v.kind;
     return true;
 }
 

@@ -77,6 +77,9 @@ struct ForceArgs {
     double* out[7];         // ax ay az jx jy jz pot (final mode)
     float2* part;           // [S][7][ni] (hi, lo) partials (partial mode)
     const DevPlan* plan;    // plan-driven launch: ni, S, jchunk come from here
+    int32_t* nn;            // nearest-neighbour evaluation: j index per i (final mode)
+    double* nn_r2;          //   and its squared distance (final mode; NULL: not wanted)
+    float2* nnpart;         //   [S][ni] (r^2, j bits) per range (partial mode)
 };
 
 struct ReduceArgs {
@@ -95,12 +98,22 @@ struct ReduceArgs {
 // Launch the pairwise kernel for one configuration; returns hipError_t.
 // jsrc 0: j tiles staged in LDS; 1: j records through wave-uniform scalar loads.
 // unr: unroll depth of the j loop (0 = 4); wpe: requested waves per SIMD (0 = none).
+// kind 0: acceleration, jerk, potential; 1: acceleration and potential only;
+// 2: kind 0 plus the nearest neighbour (ForceArgs.nn / nn_r2 / nnpart).
 hipError_t launch_force(int prec, int ipt, int tile_j, int wg, int jsrc, int unr, int wpe, bool eps0, int n_iblocks,
-                        int S, const ForceArgs& a, hipStream_t st);
-bool force_variant_exists(int prec, int ipt, int tile_j, int wg, int jsrc, int unr, int wpe, bool eps0);
+                        int S, const ForceArgs& a, hipStream_t st, int kind = 0);
+bool force_variant_exists(int prec, int ipt, int tile_j, int wg, int jsrc, int unr, int wpe, bool eps0,
+                          int kind = 0);
 int force_variant_count();
-bool force_variant_at(int k, int* prec, int* ipt, int* tj, int* wg, int* jsrc, int* unr, int* wpe, bool* eps0);
+bool force_variant_at(int k, int* prec, int* ipt, int* tj, int* wg, int* jsrc, int* unr, int* wpe, bool* eps0,
+                      int* kind);
+// Rows of ReduceArgs.out that are NULL are skipped.
 hipError_t launch_reduce(const ReduceArgs& a, hipStream_t st);
+hipError_t launch_nn_reduce(int ni, int S, const float2* nnpart, int32_t* nn, double* nn_r2, hipStream_t st);
+// Leapfrog: v += a h, x += v dt, then pack x (and m) into j records; and v += a h.
+hipError_t launch_lf_kick_drift_pack(int prec, int n, double* x, double* v, const double* acc, const double* m,
+                                     double h, double dt, float4* out, hipStream_t st);
+hipError_t launch_lf_kick(int n, double* v, const double* acc, double h, hipStream_t st);
 // Plan-driven launches (block sizes known only on the device).
 bool force_plan_variant_exists(int prec, int ipt, int tile_j, int wg);
 hipError_t launch_force_plan(int prec, int ipt, int tile_j, int wg, bool eps0, int grid, const ForceArgs& a,

@@ -86,6 +86,36 @@ def test_force_argument_errors(hostctx):
     assert "no device" in hostctx.last_error()
 
 
+def test_force_acc_nn_leapfrog_argument_errors(hostctx):
+    L = nb.lib()
+    h = hostctx.handle
+    novel = nb.Src(8, 8, 8, None, None, None, 8)
+    out3 = nb.Out(8, 8, 8, None, None, None, 8)
+    acc = lambda **kw: L.nbody_force_acc(h, None, 1, 1.0, kw.get("eps", 0.1), kw.get("ni", 10),
+                                         kw.get("I", novel), None, 10, kw.get("J", novel),
+                                         kw.get("out", out3))
+    # the force-only evaluation needs neither velocities nor jerk rows
+    assert acc() == -4
+    assert acc(eps=-1.0) == -1 and acc(ni=-2) == -1
+    nom = nb.Src(8, 8, 8, None, None, None, None)
+    assert acc(J=nom) == -1
+    o = nb.Out(8, 8, 8, None, None, None, None)
+    assert acc(out=o) == -1
+    nn = lambda **kw: L.nbody_force_nn(h, None, 1, 1.0, 0.1, 10, kw.get("I", _src()), None, 10, _src(),
+                                       _out(), kw.get("nn", 8), kw.get("r2", None))
+    assert nn() == -4
+    assert nn(nn=None) == -1 and "nn is NULL" in hostctx.last_error()
+    assert nn(r2=12) == -1
+    assert nn(I=novel) == -1                  # the jerk needs velocities
+    lf = lambda **kw: L.nbody_leapfrog(h, None, 1, 1.0, kw.get("eps", 0.1), kw.get("dt", 0.01),
+                                       kw.get("steps", 3), kw.get("n", 10), kw.get("x", 8), 8, 8,
+                                       kw.get("a", 8), kw.get("pot", None), 0)
+    assert lf() == -4
+    assert lf(steps=-1) == -1 and lf(dt=float("nan")) == -1 and lf(n=-1) == -1
+    assert lf(x=None) == -1 and lf(a=None) == -1 and lf(pot=4) == -1
+    assert lf(n=0, x=None) == -4              # nothing to move: reaches the device check
+
+
 def test_other_entry_points_validate(hostctx):
     L = nb.lib()
     h = hostctx.handle
