@@ -195,6 +195,34 @@ def batched_timing(ctx, prec, steps=32):
             "per_cluster_Gint_s": round(tot / t_per / 1e9, 1)}
 
 
+def kinds_timing(ctx, X, V, M, eps, prec, full_kernel_ms, reps=2):
+    """The force-only (acceleration + potential, 38 conventional flops per
+    interaction) and nearest-neighbour evaluations on the same N = 2^20
+    system, timed per launch with HIP events on the launch stream."""
+    import torch
+    n = X.shape[1]
+    S = torch.arange(n, dtype=torch.int32, device="cuda")
+    out = {}
+    for name, fn in (("force_only", lambda: ctx.force_acc(X, X, M, eps, prec=prec, i_self=S)),
+                     ("nearest_neighbour", lambda: ctx.force_nn(X, V, X, V, M, eps, prec=prec, i_self=S))):
+        fn()
+        torch.cuda.synchronize()
+        ctx.kernel_timing(True)
+        for _ in range(reps):
+            fn()
+        ms, launches = ctx.kernel_time()
+        ctx.kernel_timing(False)
+        ms /= max(launches, 1)
+        gint = float(n) * n / (ms * 1e-3) / 1e9
+        k = 38 if name == "force_only" else FLOPS_PER_INTERACTION
+        out[name] = {"kernel_ms": round(ms, 3), "Gint_s": round(gint, 1),
+                     "conventional_TFLOPs": round(k * gint / 1e3, 2), "flops_per_interaction": k,
+                     "pct_fp32_peak": round(100.0 * k * gint / 1e3 / FP32_PEAK_TFLOPS, 2),
+                     "time_vs_full_kernel": round(ms / full_kernel_ms, 3)}
+    out["workload"] = f"plummer1m_force (N={n}, eps={eps}), all particles, {reps} launches each"
+    return out
+
+
 def block_run(n, t_end, precs, report_every=0.0):
     """Hermite block steps on the Salpeter workload (Plummer positions and
     velocities, Salpeter masses 0.1-100 normalised to 1, eps = 1e-3,
@@ -281,8 +309,8 @@ def main():
     ap.add_argument("--block-run", action="store_true",
                     help="only run the Salpeter block-step workload (--n, --t-end) and print its JSON")
     ap.add_argument("--t-end", type=float, default=1.0)
-    ap.add_argument("--extras", default="batched,adjoint",
-                    help="comma list of extra measurements (batched, adjoint) or 'none'")
+    ap.add_argument("--extras", default="batched,adjoint,kinds",
+                    help="comma list of extra measurements (batched, adjoint, kinds) or 'none'")
     ap.add_argument("--report-every", type=float, default=0.0)
     args = ap.parse_args()
     if args.copy_calibration:
@@ -383,6 +411,9 @@ def main():
     if "adjoint" in extras:
         log("[bench] adjoint/forward timing")
         line["adjoint"] = adjoint_timing(nb, ctx, args.prec)
+    if "kinds" in extras:
+        log("[bench] force-only and nearest-neighbour evaluations")
+        line["kinds"] = kinds_timing(ctx, X, V, M, eps, args.prec, k_ms)
     if args.cpu_budget > 0:
         log("[bench] cpu baseline (oracle)")
         line["cpu_baseline"] = cpu_baseline(p, eps, args.cpu_budget)

@@ -176,6 +176,22 @@ static nbody_tile default_tile(int prec, int64_t ni, int64_t nj) {
     return t;
 }
 
+// Defaults of the force-only (kind 1) and nearest-neighbour (kind 2)
+// evaluations: the fastest shapes of the MI355X sweep at 2^20 x 2^20; small
+// problems take the small default shape.
+static nbody_tile default_tile_kind(int kind, int prec, int64_t ni, int64_t nj) {
+    nbody_tile t = default_tile(prec, ni, nj);
+    if ((double)ni * (double)nj < 4294967296.0) return t;
+    if (kind == 1 && prec == 1) {
+        t.tile_j = 128;
+        t.unroll = 0;
+    } else if (kind == 2 && prec == 1) {
+        t.ipt = 2;
+        t.unroll = 101;
+    }
+    return t;
+}
+
 static nbody_tile pick_tile(nbody_ctx* c, int prec, int64_t ni, int64_t nj) {
     nbody_tile t;
     if (c->have_override[prec]) {
@@ -195,7 +211,14 @@ static int run_force(nbody_ctx* c, hipStream_t st, int prec, double G, double ep
                      int64_t nj, const float4* jpack, double* const out[7], const nbody_tile* forced,
                      int kind = 0, int32_t* nn = nullptr, double* nn_r2 = nullptr) {
     if (ni == 0) return NBODY_OK;
-    nbody_tile t = forced ? *forced : pick_tile(c, prec, ni, nj);
+    nbody_tile t;
+    if (forced) {
+        t = *forced;
+    } else if (kind == 0 || c->have_override[prec]) {
+        t = pick_tile(c, prec, ni, nj);   // tuned entries hold kind-0 shapes only
+    } else {
+        t = default_tile_kind(kind, prec, ni, nj);
+    }
     if (t.split <= 0) t.split = choose_split(ni, nj, t);
     const bool eps0 = eps == 0.0;
     int ipt = t.ipt, tj = t.tile_j, wg = t.wg, jsrc = t.jsrc, unr = t.unroll, wpe = t.waves;
@@ -206,8 +229,8 @@ static int run_force(nbody_ctx* c, hipStream_t st, int prec, double G, double ep
             tj = 128;
             wg = 256;
         } else {
-            // the other kinds fall back to the default shape for the size
-            const nbody_tile d = default_tile(prec, ni, nj);
+            // the other kinds fall back to their default shape for the size
+            const nbody_tile d = default_tile_kind(kind, prec, ni, nj);
             ipt = d.ipt;
             tj = d.tile_j;
             wg = d.wg;
