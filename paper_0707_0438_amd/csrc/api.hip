@@ -801,7 +801,7 @@ static int pack_predicted(nbody_hermite* h, hipStream_t st, const int64_t* gate)
     return NBODY_OK;
 }
 
-static CorrectArgs correct_args(nbody_hermite* h, int n_act, const int64_t* nact_dev) {
+static CorrectArgs correct_args(nbody_hermite* h, int n_act) {
     CorrectArgs ca{};
     ca.n_act = n_act;
     ca.idx = h->idx;
@@ -818,7 +818,6 @@ static CorrectArgs correct_args(nbody_hermite* h, int n_act, const int64_t* nact
     ca.lmax = h->o.dt_max_log2;
     ca.shared = h->o.shared_dt_log2 != 0;
     ca.tnow = h->tnow;
-    ca.nact_dev = nact_dev;
     return ca;
 }
 
@@ -840,7 +839,7 @@ static int hermite_step_shared(nbody_hermite* h, hipStream_t st, int64_t t_limit
     rc = run_force(c, st, p, h->o.G, h->o.eps, n, (const float4*)c->jpack.p, h->idx, nullptr, 1, n,
                    (const float4*)c->jpack.p, h->f, nullptr);
     if (rc) return rc;
-    e = launch_correct(correct_args(h, n, nullptr), st);
+    e = launch_correct(correct_args(h, n), st);
     if (e != hipSuccess) return hip_err(c, e, "corrector launch");
     h->t_ticks = tn;
     h->steps += 1;
@@ -848,18 +847,27 @@ static int hermite_step_shared(nbody_hermite* h, hipStream_t st, int64_t t_limit
     return NBODY_OK;
 }
 
-// Block steps: select, plan, predict/pack, force, reduce, correct, all
-// driven by the device plan (block size, split, end-time gate); a step past
-// the gate leaves every state untouched.  No host synchronisation.
+// Block steps: select + predict/pack + plan (three passes), force, then
+// reduce + correct, all driven by the device plan (block size, split,
+// end-time gate); a step past the gate leaves every state untouched.  No
+// host synchronisation.
 static int hermite_enqueue_block(nbody_hermite* h, hipStream_t st) {
     nbody_ctx* c = h->ctx;
     const int n = (int)h->n;
     const int p = (int)h->o.prec;
-    hipError_t e = launch_select(n, h->t, h->dt, h->idx, h->sel2, (int64_t*)c->sel.p + 2, st);
-    if (e == hipSuccess) e = launch_plan(h->plan, h->sel2, kBlkWG * kBlkIPT, kBlkTile, n, st);
-    if (e != hipSuccess) return hip_err(c, e, "select/plan launch");
-    int rc = pack_predicted(h, st, &h->plan->n_act);
-    if (rc) return rc;
+    PackArgs pa{};
+    pa.n = n;
+    pa.prec = p;
+    pa.x = h->s[0]; pa.y = h->s[1]; pa.z = h->s[2];
+    pa.vx = h->s[3]; pa.vy = h->s[4]; pa.vz = h->s[5];
+    pa.m = h->s[12];
+    pa.ax = h->s[6]; pa.ay = h->s[7]; pa.az = h->s[8];
+    pa.jx = h->s[9]; pa.jy = h->s[10]; pa.jz = h->s[11];
+    pa.t = h->t;
+    pa.out = (float4*)c->jpack.p;
+    hipError_t e = launch_blk_front(pa, h->dt, h->idx, h->sel2, h->plan, (int64_t*)c->sel.p + 2,
+                                    kBlkWG * kBlkIPT, kBlkTile, st);
+    if (e != hipSuccess) return hip_err(c, e, "select/pack/plan launch");
     ForceArgs a{};
     a.ipack = (const float4*)c->jpack.p;
     a.iidx = h->idx;
@@ -889,17 +897,16 @@ static int hermite_enqueue_block(nbody_hermite* h, hipStream_t st) {
     r.G = h->o.G;
     for (int q = 0; q < 7; ++q) r.out[q] = h->f[q];
     r.plan = h->plan;
-    e = launch_reduce_plan(r, 1024, st);
-    if (e != hipSuccess) return hip_err(c, e, "reduce launch");
-    e = launch_correct(correct_args(h, n, &h->plan->n_act), st);
-    if (e != hipSuccess) return hip_err(c, e, "corrector launch");
+    e = launch_blk_reduce_correct(r, correct_args(h, n), 1024, st);
+    if (e != hipSuccess) return hip_err(c, e, "reduce/corrector launch");
     return NBODY_OK;
 }
 
 static int block_buffers(nbody_hermite* h) {
     nbody_ctx* c = h->ctx;
     const int64_t n = h->n;
-    int rc = dev_alloc(c, c->sel, (2 + (size_t)select_scratch_words((int)n)) * sizeof(int64_t));
+    const int words = std::max(select_scratch_words((int)n), blk_scratch_words((int)n));
+    int rc = dev_alloc(c, c->sel, (2 + (size_t)words) * sizeof(int64_t));
     // partials: S * n_act <= (2048 + nb) * per_blk <= 2049 * per_blk + n
     if (!rc) rc = dev_alloc(c, c->part, sizeof(float2) * 7 * ((size_t)2049 * kBlkWG * kBlkIPT + (size_t)n));
     if (!rc) rc = dev_alloc(c, c->jpack, sizeof(float4) * rec_words((int)h->o.prec) * (size_t)n);

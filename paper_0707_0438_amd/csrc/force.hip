@@ -426,61 +426,6 @@ __global__ __launch_bounds__(256) void reduce_wave_kernel(ReduceArgs a) {
     if (lane == 0) a.out[q][i] = reduce_finish(a, q, i, s);
 }
 
-// Plan-driven reduce: grid-stride over (quantity, i) rows, one wave each.
-__global__ __launch_bounds__(256) void reduce_plan_kernel(ReduceArgs a) {
-    const DevPlan* pl = a.plan;
-    const int n = (int)pl->n_act, S = pl->S;
-    if (n <= 0 || S <= 1) return;
-    ReduceArgs b = a;
-    b.ni = n;
-    b.S = S;
-    const int lane = threadIdx.x & 63;
-    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
-    for (int64_t w = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; w < 7 * (int64_t)n; w += nw) {
-        const int q = (int)(w / n);
-        const int i = (int)(w - (int64_t)q * n);
-        double s = 0.0;
-        for (int sp = lane; sp < S; sp += 64) {
-            const float2 p = b.part[((size_t)sp * 7 + q) * n + i];
-            s += (double)p.x;
-            s += (double)p.y;
-        }
-        for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
-        if (lane == 0) b.out[q][i] = reduce_finish(b, q, i, s);
-    }
-}
-
-hipError_t launch_reduce_plan(const ReduceArgs& a, int grid, hipStream_t st) {
-    hipLaunchKernelGGL(reduce_plan_kernel, dim3(grid), dim3(256), 0, st, a);
-    return hipGetLastError();
-}
-
-// One thread turns the selected block (sel2 = n_act, t_next) into the launch
-// geometry and applies the end-time gate of the current advance.
-__global__ void plan_kernel(DevPlan* p, const int64_t* __restrict__ sel2, int per_blk, int tile_j, int nj) {
-    const int64_t n = sel2[0], tn = sel2[1];
-    if (n <= 0 || tn > p->t_limit) {
-        p->n_act = 0;
-        p->frozen = 1;
-        return;
-    }
-    int nb, S, jc;
-    split_plan(n, nj, per_blk, tile_j, 0, &nb, &S, &jc);
-    p->n_act = n;
-    p->t_next = tn;
-    p->nb = nb;
-    p->S = S;
-    p->jchunk = jc;
-    p->steps += 1;
-    p->sum_active += n;
-    p->t_last = tn;
-}
-
-hipError_t launch_plan(DevPlan* p, const int64_t* sel2, int per_blk, int tile_j, int nj, hipStream_t st) {
-    hipLaunchKernelGGL(plan_kernel, dim3(1), dim3(1), 0, st, p, sel2, per_blk, tile_j, nj);
-    return hipGetLastError();
-}
-
 // Nearest neighbour over the j-ranges: the smallest r^2, the lower range
 // (hence the lower j) on ties.
 __global__ __launch_bounds__(256) void nn_reduce_kernel(int ni, int S, const float2* __restrict__ nnpart,
@@ -515,76 +460,6 @@ hipError_t launch_reduce(const ReduceArgs& a, hipStream_t st) {
     } else {
         hipLaunchKernelGGL(reduce_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a);
     }
-    return hipGetLastError();
-}
-
-template <int PREC>
-__global__ __launch_bounds__(256) void pack_kernel(PackArgs a) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= a.n) return;
-    if (a.gate && *a.gate == 0) return;
-    double px = a.x[k], py = a.y[k], pz = a.z[k];
-    double qx = a.vx ? a.vx[k] : 0.0, qy = a.vy ? a.vy[k] : 0.0, qz = a.vz ? a.vz[k] : 0.0;
-    if (a.t) {
-        const double D = (double)(*a.tnext - a.t[k]) * kTick;
-        predict1(px, qx, a.ax[k], a.jx[k], D, px, qx);
-        predict1(py, qy, a.ay[k], a.jy[k], D, py, qy);
-        predict1(pz, qz, a.az[k], a.jz[k], D, pz, qz);
-    }
-    const float m = a.m ? (float)a.m[k] : 0.f;
-    if (PREC == 0) {
-        a.out[2 * (size_t)k] = make_float4((float)px, (float)py, (float)pz, m);
-        a.out[2 * (size_t)k + 1] = make_float4((float)qx, (float)qy, (float)qz, 0.f);
-    } else {
-        const float hx = (float)px, hy = (float)py, hz = (float)pz;
-        const float lx = (float)(px - (double)hx), ly = (float)(py - (double)hy),
-                    lz = (float)(pz - (double)hz);
-        a.out[3 * (size_t)k] = make_float4(hx, hy, hz, m);
-        a.out[3 * (size_t)k + 1] = make_float4((float)qx, (float)qy, (float)qz, 0.f);
-        a.out[3 * (size_t)k + 2] = make_float4(lx, ly, lz, 0.f);
-    }
-}
-
-hipError_t launch_pack(const PackArgs& a, hipStream_t st) {
-    if (a.n <= 0) return hipSuccess;
-    const dim3 g((a.n + 255) / 256), b(256);
-    if (a.prec == 0)
-        hipLaunchKernelGGL(pack_kernel<0>, g, b, 0, st, a);
-    else
-        hipLaunchKernelGGL(pack_kernel<1>, g, b, 0, st, a);
-    return hipGetLastError();
-}
-
-__global__ __launch_bounds__(256) void predict_all_kernel(int n, const double* __restrict__ x,
-                                                          const double* __restrict__ y,
-                                                          const double* __restrict__ z,
-                                                          const double* __restrict__ vx,
-                                                          const double* __restrict__ vy,
-                                                          const double* __restrict__ vz,
-                                                          const double* __restrict__ ax,
-                                                          const double* __restrict__ ay,
-                                                          const double* __restrict__ az,
-                                                          const double* __restrict__ jx,
-                                                          const double* __restrict__ jy,
-                                                          const double* __restrict__ jz,
-                                                          const int64_t* __restrict__ t,
-                                                          const int64_t* __restrict__ tnext,
-                                                          double* ox, double* oy, double* oz,
-                                                          double* ovx, double* ovy, double* ovz) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n) return;
-    const double D = (double)(*tnext - t[k]) * kTick;
-    predict1(x[k], vx[k], ax[k], jx[k], D, ox[k], ovx[k]);
-    predict1(y[k], vy[k], ay[k], jy[k], D, oy[k], ovy[k]);
-    predict1(z[k], vz[k], az[k], jz[k], D, oz[k], ovz[k]);
-}
-
-hipError_t launch_predict_all(int n, const double* const* s, const int64_t* t, const int64_t* tnext,
-                              double* const* o, hipStream_t st) {
-    if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(predict_all_kernel, dim3((n + 255) / 256), dim3(256), 0, st, n, s[0], s[1],
-                       s[2], s[3], s[4], s[5], s[6], s[7], s[8], s[9], s[10], s[11], t, tnext, o[0],
-                       o[1], o[2], o[3], o[4], o[5]);
     return hipGetLastError();
 }
 

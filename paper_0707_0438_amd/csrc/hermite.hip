@@ -111,12 +111,13 @@ __device__ __forceinline__ int64_t block_sum_i64(int64_t v, int64_t* red) {
     return r;
 }
 
+template <int CH>
 __global__ __launch_bounds__(kSelWG) void select_min_kernel(int n, const int64_t* __restrict__ t,
                                                             const int64_t* __restrict__ dt,
                                                             int64_t* __restrict__ gmin) {
     __shared__ int64_t red[kSelWG / 64];
-    const int base = blockIdx.x * kSelChunk;
-    const int end = min(n, base + kSelChunk);
+    const int base = blockIdx.x * CH;
+    const int end = min(n, base + CH);
     int64_t m = INT64_MAX;
     for (int k = base + threadIdx.x; k < end; k += kSelWG) {
         const int64_t v = t[k] + dt[k];
@@ -196,9 +197,130 @@ hipError_t launch_select(int n, const int64_t* t, const int64_t* dt, int32_t* id
     const int G = (n + kSelChunk - 1) / kSelChunk;
     int64_t* gmin = scratch;
     int64_t* gcnt = scratch + G;
-    hipLaunchKernelGGL(select_min_kernel, dim3(G), dim3(kSelWG), 0, st, n, t, dt, gmin);
+    hipLaunchKernelGGL(select_min_kernel<kSelChunk>, dim3(G), dim3(kSelWG), 0, st, n, t, dt, gmin);
     hipLaunchKernelGGL(select_count_kernel, dim3(G), dim3(kSelWG), 0, st, n, G, t, dt, gmin, gcnt, out2);
     hipLaunchKernelGGL(select_write_kernel, dim3(G), dim3(kSelWG), 0, st, n, G, t, dt, gcnt, out2, idx);
+    return hipGetLastError();
+}
+
+// ---- block-step front end ---------------------------------------------------
+// The selection of a block step fused with the work that depends only on its
+// result, in three passes over chunks of kBlkChunk entries:
+//   1. chunk minima of t + dt (select_min_kernel<kBlkChunk>);
+//   2. the global minimum t_next, each chunk's count of particles due at
+//      t_next, and the prediction of every particle of the chunk to t_next
+//      packed into j records;
+//   3. each chunk's offset and the ordered compaction of its due indices,
+//      and (one thread) the block plan: size, launch geometry of the
+//      pairwise kernel, statistics.
+// A step whose t_next lies beyond the plan's end time changes nothing and
+// marks the plan frozen.  Integer selection, so the block is exact.
+constexpr int kBlkChunk = 1024;
+constexpr int kBlkPer = kBlkChunk / kSelWG;
+
+template <int PREC>
+__global__ __launch_bounds__(kSelWG) void blk_count_pack_kernel(int G, const int64_t* __restrict__ dt,
+                                                                const int64_t* __restrict__ gmin,
+                                                                int64_t* __restrict__ gcnt,
+                                                                int64_t* __restrict__ sel2,
+                                                                const DevPlan* __restrict__ plan, PackArgs pa) {
+    __shared__ int64_t red[kSelWG / 64];
+    int64_t m = INT64_MAX;
+    for (int g = threadIdx.x; g < G; g += kSelWG) m = gmin[g] < m ? gmin[g] : m;
+    const int64_t tn = block_min_i64(m, red);
+    const int base = blockIdx.x * kBlkChunk;
+    const int end = min(pa.n, base + kBlkChunk);
+    int64_t c = 0;
+    for (int k = base + threadIdx.x; k < end; k += kSelWG) c += (pa.t[k] + dt[k] == tn) ? 1 : 0;
+    c = block_sum_i64(c, red);
+    if (threadIdx.x == 0) {
+        gcnt[blockIdx.x] = c;
+        if (blockIdx.x == 0) sel2[1] = tn;
+    }
+    if (tn > plan->t_limit) return;
+    for (int k = base + threadIdx.x; k < end; k += kSelWG) pack_one<PREC>(pa, k, tn);
+}
+
+__global__ __launch_bounds__(kSelWG) void blk_write_plan_kernel(int n, int G, const int64_t* __restrict__ t,
+                                                                const int64_t* __restrict__ dt,
+                                                                const int64_t* __restrict__ gcnt,
+                                                                int64_t* __restrict__ sel2,
+                                                                int32_t* __restrict__ idx, DevPlan* plan,
+                                                                int per_blk, int tile_j) {
+    __shared__ int64_t red[kSelWG / 64];
+    __shared__ int wsum[kSelWG / 64];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int64_t tn = sel2[1];
+    int64_t before = 0, total = 0;
+    for (int g = tid; g < G; g += kSelWG) {
+        total += gcnt[g];
+        before += g < (int)blockIdx.x ? gcnt[g] : 0;
+    }
+    before = block_sum_i64(before, red);
+    total = block_sum_i64(total, red);
+    const bool go = total > 0 && tn <= plan->t_limit;
+    if (go) {
+        const int k0 = blockIdx.x * kBlkChunk + tid * kBlkPer;
+        int cnt = 0;
+#pragma unroll
+        for (int u = 0; u < kBlkPer; ++u) {
+            const int k = k0 + u;
+            cnt += (k < n && t[k] + dt[k] == tn) ? 1 : 0;
+        }
+        int incl = cnt;
+        for (int off = 1; off < 64; off <<= 1) {
+            const int o = __shfl_up(incl, off);
+            if (lane >= off) incl += o;
+        }
+        if (lane == 63) wsum[w] = incl;
+        __syncthreads();
+        int wbase = 0;
+        for (int k = 0; k < w; ++k) wbase += wsum[k];
+        int64_t pos = before + wbase + incl - cnt;
+#pragma unroll
+        for (int u = 0; u < kBlkPer; ++u) {
+            const int k = k0 + u;
+            if (k < n && t[k] + dt[k] == tn) idx[pos++] = k;
+        }
+    }
+    if (blockIdx.x == 0 && tid == 0) {
+        sel2[0] = total;
+        if (!go) {
+            plan->n_act = 0;
+            plan->frozen = 1;
+        } else {
+            int nb, S, jc;
+            split_plan(total, n, per_blk, tile_j, 0, &nb, &S, &jc);
+            plan->n_act = total;
+            plan->t_next = tn;
+            plan->nb = nb;
+            plan->S = S;
+            plan->jchunk = jc;
+            plan->steps += 1;
+            plan->sum_active += total;
+            plan->t_last = tn;
+        }
+    }
+}
+
+int blk_scratch_words(int n) { return 2 * ((n + kBlkChunk - 1) / kBlkChunk); }
+
+hipError_t launch_blk_front(const PackArgs& pa, const int64_t* dt, int32_t* idx, int64_t* sel2, DevPlan* plan,
+                            int64_t* scratch, int per_blk, int tile_j, hipStream_t st) {
+    const int n = pa.n;
+    if (n <= 0) return hipErrorInvalidValue;
+    const int G = (n + kBlkChunk - 1) / kBlkChunk;
+    int64_t* gmin = scratch;
+    int64_t* gcnt = scratch + G;
+    hipLaunchKernelGGL(select_min_kernel<kBlkChunk>, dim3(G), dim3(kSelWG), 0, st, n, pa.t, dt, gmin);
+    if (pa.prec == 0)
+        hipLaunchKernelGGL(blk_count_pack_kernel<0>, dim3(G), dim3(kSelWG), 0, st, G, dt, gmin, gcnt, sel2, plan,
+                           pa);
+    else
+        hipLaunchKernelGGL(blk_count_pack_kernel<1>, dim3(G), dim3(kSelWG), 0, st, G, dt, gmin, gcnt, sel2, plan,
+                           pa);
+    hipLaunchKernelGGL(blk_write_plan_kernel, dim3(G), dim3(kSelWG), 0, st, n, G, pa.t, dt, gcnt, sel2, idx, plan,
+                       per_blk, tile_j);
     return hipGetLastError();
 }
 
@@ -211,20 +333,25 @@ __device__ __forceinline__ double norm3(double a, double b, double c) { return s
 //   x1 = x_p + a2 D^4/24 + a3 D^5/120,  v1 = v_p + a2 D^3/6 + a3 D^4/24,
 // then the Aarseth criterion with a2 carried to the new time, and the
 // power-of-two level rule.
-__device__ __forceinline__ void correct_one(const CorrectArgs& a, int c);
+__device__ __forceinline__ void correct_core(const CorrectArgs& a, int c, const double* a1in, const double* j1in);
+__device__ __forceinline__ void correct_one(const CorrectArgs& a, int c) {
+    double a1[3], j1[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        a1[k] = a.f[k][c];
+        j1[k] = a.f[3 + k][c];
+    }
+    correct_core(a, c, a1, j1);
+}
 
 __global__ __launch_bounds__(256) void correct_kernel(CorrectArgs a) {
-    if (a.nact_dev) {
-        const int n = (int)*a.nact_dev;
-        for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x) correct_one(a, c);
-        return;
-    }
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= a.n_act) return;
     correct_one(a, c);
 }
 
-__device__ __forceinline__ void correct_one(const CorrectArgs& a, int c) {
+__device__ __forceinline__ void correct_core(const CorrectArgs& a, int c, const double* a1in,
+                                             const double* j1in) {
     const int i = a.idx[c];
     const int64_t tn = *a.tnext;
     if (c == 0 && a.tnow) *a.tnow = tn;
@@ -240,8 +367,8 @@ __device__ __forceinline__ void correct_one(const CorrectArgs& a, int c) {
     for (int k = 0; k < 3; ++k) {
         double xp, vp;
         predict1(X[k][i], V[k][i], A[k][i], J[k][i], Dp, xp, vp);
-        a1[k] = a.f[k][c];
-        j1[k] = a.f[3 + k][c];
+        a1[k] = a1in[k];
+        j1[k] = j1in[k];
         const double a0 = A[k][i], j0 = J[k][i];
         const double da = a0 - a1[k];
         a2[k] = (-6.0 * da - D * (4.0 * j0 + 2.0 * j1[k])) * iD2;
@@ -264,9 +391,7 @@ __device__ __forceinline__ void correct_one(const CorrectArgs& a, int c) {
 
 hipError_t launch_correct(const CorrectArgs& a, hipStream_t st) {
     if (a.n_act <= 0) return hipSuccess;
-    // plan-driven: n_act is an upper bound (grid-stride up to the device count)
-    const int grid = a.nact_dev ? (a.n_act + 255) / 256 < 1024 ? (a.n_act + 255) / 256 : 1024
-                                : (a.n_act + 255) / 256;
+    const int grid = (a.n_act + 255) / 256;
     hipLaunchKernelGGL(correct_kernel, dim3(grid), dim3(256), 0, st, a);
     return hipGetLastError();
 }
@@ -281,6 +406,44 @@ __global__ __launch_bounds__(256) void init_dt_kernel(InitDtArgs a) {
     const double na = norm3(a.ax[i], a.ay[i], a.az[i]);
     const double nj = norm3(a.jx[i], a.jy[i], a.jz[i]);
     a.dt[i] = block_level(a.eta_s * na / nj, 0, 0, a.lmin, a.lmax);
+}
+
+// Block steps: the float64 reduction of the split partials (the same
+// lane-strided sums and butterfly as the wave-per-row split reduce, so the same
+// bits) fused with the corrector, one wave per active particle.  Without a
+// split the pairwise kernel has written the forces and only the corrector
+// runs.
+__global__ __launch_bounds__(256) void blk_reduce_correct_kernel(ReduceArgs r, CorrectArgs ca) {
+    const DevPlan* pl = r.plan;
+    const int n = (int)pl->n_act, S = pl->S;
+    if (n <= 0) return;
+    if (S <= 1) {
+        for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x) correct_one(ca, c);
+        return;
+    }
+    const int lane = threadIdx.x & 63;
+    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t w = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; w < n; w += nw) {
+        const int c = (int)w;
+        double f[6];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+            double s = 0.0;
+            for (int sp = lane; sp < S; sp += 64) {
+                const float2 p = r.part[((size_t)sp * 7 + q) * n + c];
+                s += (double)p.x;
+                s += (double)p.y;
+            }
+            for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+            f[q] = r.G * s;
+        }
+        if (lane == 0) correct_core(ca, c, f, f + 3);
+    }
+}
+
+hipError_t launch_blk_reduce_correct(const ReduceArgs& r, const CorrectArgs& ca, int grid, hipStream_t st) {
+    hipLaunchKernelGGL(blk_reduce_correct_kernel, dim3(grid), dim3(256), 0, st, r, ca);
+    return hipGetLastError();
 }
 
 hipError_t launch_init_dt(const InitDtArgs& a, hipStream_t st) {

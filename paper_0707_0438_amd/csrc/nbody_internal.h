@@ -118,8 +118,6 @@ hipError_t launch_lf_kick(int n, double* v, const double* acc, double h, hipStre
 bool force_plan_variant_exists(int prec, int ipt, int tile_j, int wg);
 hipError_t launch_force_plan(int prec, int ipt, int tile_j, int wg, bool eps0, int grid, const ForceArgs& a,
                              hipStream_t st);
-hipError_t launch_reduce_plan(const ReduceArgs& a, int grid, hipStream_t st);
-hipError_t launch_plan(DevPlan* p, const int64_t* sel2, int per_blk, int tile_j, int nj, hipStream_t st);
 
 // ---- batched clusters ----
 struct BatchArgs {
@@ -174,9 +172,17 @@ struct CorrectArgs {
     double eta;
     int lmin, lmax, shared;           // shared != 0: keep dt
     int64_t* tnow;                    // receives the block time (written by one thread; may be NULL)
-    const int64_t* nact_dev;          // device block size (plan-driven launch) or NULL
 };
 hipError_t launch_correct(const CorrectArgs& a, hipStream_t st);
+
+// Block-step front end: selection, prediction/packing of all j to the block
+// time, and the device plan (see hermite.hip).  pa.t and pa.n give the
+// ticks and count; scratch holds blk_scratch_words(n) int64 words.
+int blk_scratch_words(int n);
+hipError_t launch_blk_front(const PackArgs& pa, const int64_t* dt, int32_t* idx, int64_t* sel2, DevPlan* plan,
+                            int64_t* scratch, int per_blk, int tile_j, hipStream_t st);
+// Block steps: split reduce (when the plan has S > 1) fused with the corrector.
+hipError_t launch_blk_reduce_correct(const ReduceArgs& r, const CorrectArgs& ca, int grid, hipStream_t st);
 
 // First steps after the initial force evaluation.
 struct InitDtArgs {
@@ -248,6 +254,32 @@ __device__ __forceinline__ void predict1(double x, double v, double ac, double j
                                          double& xp, double& vp) {
     xp = x + D * (v + D * (0.5 * ac + D * (jk * (1.0 / 6.0))));
     vp = v + D * (ac + D * (0.5 * jk));
+}
+
+// Predict particle k to tick tn (when a.t is given) and write its j record:
+// float32 position (DS: hi = fl32(x), lo = fl32(x - hi)), mass, velocity.
+template <int PREC>
+__device__ __forceinline__ void pack_one(const PackArgs& a, int k, int64_t tn) {
+    double px = a.x[k], py = a.y[k], pz = a.z[k];
+    double qx = a.vx ? a.vx[k] : 0.0, qy = a.vy ? a.vy[k] : 0.0, qz = a.vz ? a.vz[k] : 0.0;
+    if (a.t) {
+        const double D = (double)(tn - a.t[k]) * kTick;
+        predict1(px, qx, a.ax[k], a.jx[k], D, px, qx);
+        predict1(py, qy, a.ay[k], a.jy[k], D, py, qy);
+        predict1(pz, qz, a.az[k], a.jz[k], D, pz, qz);
+    }
+    const float m = a.m ? (float)a.m[k] : 0.f;
+    if (PREC == 0) {
+        a.out[2 * (size_t)k] = make_float4((float)px, (float)py, (float)pz, m);
+        a.out[2 * (size_t)k + 1] = make_float4((float)qx, (float)qy, (float)qz, 0.f);
+    } else {
+        const float hx = (float)px, hy = (float)py, hz = (float)pz;
+        const float lx = (float)(px - (double)hx), ly = (float)(py - (double)hy),
+                    lz = (float)(pz - (double)hz);
+        a.out[3 * (size_t)k] = make_float4(hx, hy, hz, m);
+        a.out[3 * (size_t)k + 1] = make_float4((float)qx, (float)qy, (float)qz, 0.f);
+        a.out[3 * (size_t)k + 2] = make_float4(lx, ly, lz, 0.f);
+    }
 }
 
 // j index of the particle that i-slot `ii` is (or -1): see ForceArgs::self_mode.
