@@ -37,6 +37,12 @@ EXPORTS = [
     "nbody_autotune_batched", "nbody_force_acc", "nbody_force_nn", "nbody_leapfrog",
 ]
 
+#: The GRAPE-6-style interface (include/nbody_grape.h).
+GRAPE_EXPORTS = [
+    "GPU_open", "GPU_close", "GPU_npipes", "GPU_set_j_particle", "GPU_set_ti", "GPUcalc_firsthalf",
+    "GPUcalc_lasthalf", "GPUcalc_lasthalf2", "GPU_set_nn", "GPU_set_precision", "GPU_last_error",
+]
+
 ERRORS = {0: "OK", -1: "NBODY_ERR_ARG", -2: "NBODY_ERR_NOMEM", -3: "NBODY_ERR_DEVICE",
           -4: "NBODY_ERR_UNSUPPORTED", -5: "NBODY_ERR_STATE"}
 
@@ -131,6 +137,17 @@ def lib():
         "nbody_force_acc": ([P, P, I, D, D, I64, Src, P, I64, Src, Out], I),
         "nbody_force_nn": ([P, P, I, D, D, I64, Src, P, I64, Src, Out, P, P], I),
         "nbody_leapfrog": ([P, P, I, D, D, D, I, I64, P, P, P, P, P, I], I),
+        "GPU_open": ([I], I),
+        "GPU_close": ([I], I),
+        "GPU_npipes": ([], I),
+        "GPU_set_j_particle": ([I, I, I, D, D, P, P, P, P], I),
+        "GPU_set_ti": ([I, D], I),
+        "GPUcalc_firsthalf": ([I, I, I, P, P, P, D], I),
+        "GPUcalc_lasthalf": ([I, I, P, P, P], I),
+        "GPUcalc_lasthalf2": ([I, I, P, P, P, P], I),
+        "GPU_set_nn": ([I, I], I),
+        "GPU_set_precision": ([I, I], I),
+        "GPU_last_error": ([I], C.c_char_p),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -592,3 +609,58 @@ class Hermite:
     def load(self, blob: bytes, stream=None):
         buf = C.create_string_buffer(blob, len(blob))
         self.ctx._check(lib().nbody_hermite_load(self._h, _stream(stream), buf), "nbody_hermite_load")
+
+
+class Grape:
+    """The GRAPE-6-style calls of include/nbody_grape.h on one cluster, with
+    numpy marshalling (host arrays, as the interface takes)."""
+
+    def __init__(self, clusterid: int = 0):
+        self.id = int(clusterid)
+        self._call("GPU_open", self.id)
+
+    def _call(self, name, *args):
+        rc = getattr(lib(), name)(*args)
+        if rc != 0:
+            raise NBodyError(rc, f"{name}: {lib().GPU_last_error(self.id).decode(errors='replace')}")
+
+    def close(self):
+        self._call("GPU_close", self.id)
+
+    def set_j_particle(self, address, index, tj, mass, x, v, a, j):
+        import numpy as np
+        vec = [np.ascontiguousarray(q, dtype=np.float64) for q in (x, v, a, j)]
+        self._call("GPU_set_j_particle", self.id, int(address), int(index), float(tj), float(mass),
+                   *[q.ctypes.data_as(C.c_void_p) for q in vec])
+
+    def set_ti(self, ti):
+        self._call("GPU_set_ti", self.id, float(ti))
+
+    def set_nn(self, enable):
+        self._call("GPU_set_nn", self.id, 1 if enable else 0)
+
+    def set_precision(self, prec):
+        self._call("GPU_set_precision", self.id, PREC[prec])
+
+    def calc_firsthalf(self, nj, index, xi, vi, eps2):
+        """xi, vi: (ni, 3) arrays; index: (ni,) identities."""
+        import numpy as np
+        idx = np.ascontiguousarray(index, dtype=np.int32)
+        xi = np.ascontiguousarray(xi, dtype=np.float64).reshape(-1, 3)
+        vi = np.ascontiguousarray(vi, dtype=np.float64).reshape(-1, 3)
+        self._keep = (idx, xi, vi)
+        ptr = lambda q: q.ctypes.data_as(C.c_void_p) if q.size else None
+        self._call("GPUcalc_firsthalf", self.id, int(nj), idx.size, ptr(idx), ptr(xi), ptr(vi), float(eps2))
+
+    def calc_lasthalf(self, ni, nn=False):
+        """Returns (acc (ni, 3), jerk (ni, 3), pot (ni,)) and, with nn, the
+        nearest-neighbour identities (ni,)."""
+        import numpy as np
+        acc = np.empty((ni, 3)); jerk = np.empty((ni, 3)); pot = np.empty(ni)
+        ptr = lambda q: q.ctypes.data_as(C.c_void_p) if q.size else None
+        if nn:
+            nnb = np.empty(ni, dtype=np.int32)
+            self._call("GPUcalc_lasthalf2", self.id, int(ni), ptr(acc), ptr(jerk), ptr(pot), ptr(nnb))
+            return acc, jerk, pot, nnb
+        self._call("GPUcalc_lasthalf", self.id, int(ni), ptr(acc), ptr(jerk), ptr(pot))
+        return acc, jerk, pot

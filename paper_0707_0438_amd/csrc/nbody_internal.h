@@ -256,14 +256,14 @@ __device__ __forceinline__ void predict1(double x, double v, double ac, double j
     vp = v + D * (ac + D * (0.5 * jk));
 }
 
-// Predict particle k to tick tn (when a.t is given) and write its j record:
-// float32 position (DS: hi = fl32(x), lo = fl32(x - hi)), mass, velocity.
+// Predict particle k over the interval D (when `predict`) and write its j
+// record: float32 position (DS: hi = fl32(x), lo = fl32(x - hi)), mass,
+// velocity.
 template <int PREC>
-__device__ __forceinline__ void pack_one(const PackArgs& a, int k, int64_t tn) {
+__device__ __forceinline__ void pack_one_dt(const PackArgs& a, int k, bool predict, double D) {
     double px = a.x[k], py = a.y[k], pz = a.z[k];
     double qx = a.vx ? a.vx[k] : 0.0, qy = a.vy ? a.vy[k] : 0.0, qz = a.vz ? a.vz[k] : 0.0;
-    if (a.t) {
-        const double D = (double)(tn - a.t[k]) * kTick;
+    if (predict) {
         predict1(px, qx, a.ax[k], a.jx[k], D, px, qx);
         predict1(py, qy, a.ay[k], a.jy[k], D, py, qy);
         predict1(pz, qz, a.az[k], a.jz[k], D, pz, qz);
@@ -280,6 +280,13 @@ __device__ __forceinline__ void pack_one(const PackArgs& a, int k, int64_t tn) {
         a.out[3 * (size_t)k + 1] = make_float4((float)qx, (float)qy, (float)qz, 0.f);
         a.out[3 * (size_t)k + 2] = make_float4(lx, ly, lz, 0.f);
     }
+}
+
+// The same with the interval from the particle's tick a.t[k] to tick tn
+// (no prediction when a.t is NULL).
+template <int PREC>
+__device__ __forceinline__ void pack_one(const PackArgs& a, int k, int64_t tn) {
+    pack_one_dt<PREC>(a, k, a.t != nullptr, a.t ? (double)(tn - a.t[k]) * kTick : 0.0);
 }
 
 // j index of the particle that i-slot `ii` is (or -1): see ForceArgs::self_mode.

@@ -16,16 +16,20 @@ import paper_0707_0438_amd as nb
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "nbody.h")
+GRAPE_HEADER = os.path.join(ROOT, "include", "nbody_grape.h")
 
 
-def declared_functions():
-    src = open(HEADER).read()
-    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(nbody_[a-z_0-9]+)\s*\(", src)))
+def declared_functions(header=None):
+    names = set()
+    for h in ([header] if header else [HEADER, GRAPE_HEADER]):
+        src = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
+        names |= set(re.findall(r"\b(nbody_[a-z_0-9]+|GPU[A-Za-z_0-9]*)\s*\(", src))
+    return sorted(names)
 
 
 def test_header_declarations_match_binding_list():
-    assert declared_functions() == sorted(nb.EXPORTS)
+    assert declared_functions(HEADER) == sorted(nb.EXPORTS)
+    assert declared_functions(GRAPE_HEADER) == sorted(nb.GRAPE_EXPORTS)
 
 
 def test_library_exports_every_declared_symbol():
@@ -150,6 +154,22 @@ def test_other_entry_points_validate(hostctx):
     assert L.nbody_hermite_create(h, C.byref(hp), 100, C.byref(o)) == -4
     assert L.nbody_hermite_step(None, None, None, None) == -1
     assert L.nbody_destroy(None) == 0
+
+
+def test_grape_interface_validates_without_a_device():
+    L = nb.lib()
+    import ctypes as C
+    v = (C.c_double * 3)(0.0, 0.0, 0.0)
+    assert L.GPU_open(-1) == -1 and L.GPU_open(16) == -1
+    assert L.GPU_close(-1) == -1 and L.GPU_close(3) == 0          # closing a closed cluster
+    # every call on a cluster that is not open is an argument error
+    assert L.GPU_set_j_particle(3, 0, 0, 0.0, 1.0, v, v, v, v) == -1
+    assert L.GPU_set_ti(3, 0.0) == -1
+    assert L.GPUcalc_firsthalf(3, 0, 0, None, None, None, 0.0) == -1
+    assert L.GPUcalc_lasthalf(3, 0, None, None, None) == -1
+    assert L.GPU_set_nn(3, 1) == -1 and L.GPU_set_precision(3, 1) == -1
+    assert L.GPU_last_error(99) == b"cluster id out of range"
+    assert L.GPU_npipes() > 0
 
 
 def test_create_rejects_bad_device():
