@@ -111,13 +111,12 @@ __device__ __forceinline__ int64_t block_sum_i64(int64_t v, int64_t* red) {
     return r;
 }
 
-template <int CH>
 __global__ __launch_bounds__(kSelWG) void select_min_kernel(int n, const int64_t* __restrict__ t,
                                                             const int64_t* __restrict__ dt,
                                                             int64_t* __restrict__ gmin) {
     __shared__ int64_t red[kSelWG / 64];
-    const int base = blockIdx.x * CH;
-    const int end = min(n, base + CH);
+    const int base = blockIdx.x * kSelChunk;
+    const int end = min(n, base + kSelChunk);
     int64_t m = INT64_MAX;
     for (int k = base + threadIdx.x; k < end; k += kSelWG) {
         const int64_t v = t[k] + dt[k];
@@ -197,7 +196,7 @@ hipError_t launch_select(int n, const int64_t* t, const int64_t* dt, int32_t* id
     const int G = (n + kSelChunk - 1) / kSelChunk;
     int64_t* gmin = scratch;
     int64_t* gcnt = scratch + G;
-    hipLaunchKernelGGL(select_min_kernel<kSelChunk>, dim3(G), dim3(kSelWG), 0, st, n, t, dt, gmin);
+    hipLaunchKernelGGL(select_min_kernel, dim3(G), dim3(kSelWG), 0, st, n, t, dt, gmin);
     hipLaunchKernelGGL(select_count_kernel, dim3(G), dim3(kSelWG), 0, st, n, G, t, dt, gmin, gcnt, out2);
     hipLaunchKernelGGL(select_write_kernel, dim3(G), dim3(kSelWG), 0, st, n, G, t, dt, gcnt, out2, idx);
     return hipGetLastError();
@@ -205,8 +204,9 @@ hipError_t launch_select(int n, const int64_t* t, const int64_t* dt, int32_t* id
 
 // ---- block-step front end ---------------------------------------------------
 // The selection of a block step fused with the work that depends only on its
-// result, in three passes over chunks of kBlkChunk entries:
-//   1. chunk minima of t + dt (select_min_kernel<kBlkChunk>);
+// result, in three passes over chunks of `ch` entries (a power of two chosen
+// so that about kBlkGroups work-groups share the particles):
+//   1. chunk minima of t + dt;
 //   2. the global minimum t_next, each chunk's count of particles due at
 //      t_next, and the prediction of every particle of the chunk to t_next
 //      packed into j records;
@@ -215,11 +215,30 @@ hipError_t launch_select(int n, const int64_t* t, const int64_t* dt, int32_t* id
 //      pairwise kernel, statistics.
 // A step whose t_next lies beyond the plan's end time changes nothing and
 // marks the plan frozen.  Integer selection, so the block is exact.
-constexpr int kBlkChunk = 1024;
-constexpr int kBlkPer = kBlkChunk / kSelWG;
+constexpr int kBlkGroups = 256;
+
+__host__ __device__ inline int blk_chunk(int n) {
+    int ch = kSelWG;
+    while ((int64_t)ch * kBlkGroups < n) ch *= 2;
+    return ch;
+}
+
+__global__ __launch_bounds__(kSelWG) void blk_min_kernel(int n, int ch, const int64_t* __restrict__ t,
+                                                         const int64_t* __restrict__ dt, int64_t* __restrict__ gmin) {
+    __shared__ int64_t red[kSelWG / 64];
+    const int base = blockIdx.x * ch;
+    const int end = min(n, base + ch);
+    int64_t m = INT64_MAX;
+    for (int k = base + threadIdx.x; k < end; k += kSelWG) {
+        const int64_t v = t[k] + dt[k];
+        m = v < m ? v : m;
+    }
+    m = block_min_i64(m, red);
+    if (threadIdx.x == 0) gmin[blockIdx.x] = m;
+}
 
 template <int PREC>
-__global__ __launch_bounds__(kSelWG) void blk_count_pack_kernel(int G, const int64_t* __restrict__ dt,
+__global__ __launch_bounds__(kSelWG) void blk_count_pack_kernel(int ch, int G, const int64_t* __restrict__ dt,
                                                                 const int64_t* __restrict__ gmin,
                                                                 int64_t* __restrict__ gcnt,
                                                                 int64_t* __restrict__ sel2,
@@ -228,8 +247,8 @@ __global__ __launch_bounds__(kSelWG) void blk_count_pack_kernel(int G, const int
     int64_t m = INT64_MAX;
     for (int g = threadIdx.x; g < G; g += kSelWG) m = gmin[g] < m ? gmin[g] : m;
     const int64_t tn = block_min_i64(m, red);
-    const int base = blockIdx.x * kBlkChunk;
-    const int end = min(pa.n, base + kBlkChunk);
+    const int base = blockIdx.x * ch;
+    const int end = min(pa.n, base + ch);
     int64_t c = 0;
     for (int k = base + threadIdx.x; k < end; k += kSelWG) c += (pa.t[k] + dt[k] == tn) ? 1 : 0;
     c = block_sum_i64(c, red);
@@ -241,7 +260,7 @@ __global__ __launch_bounds__(kSelWG) void blk_count_pack_kernel(int G, const int
     for (int k = base + threadIdx.x; k < end; k += kSelWG) pack_one<PREC>(pa, k, tn);
 }
 
-__global__ __launch_bounds__(kSelWG) void blk_write_plan_kernel(int n, int G, const int64_t* __restrict__ t,
+__global__ __launch_bounds__(kSelWG) void blk_write_plan_kernel(int n, int ch, int G, const int64_t* __restrict__ t,
                                                                 const int64_t* __restrict__ dt,
                                                                 const int64_t* __restrict__ gcnt,
                                                                 int64_t* __restrict__ sel2,
@@ -260,10 +279,10 @@ __global__ __launch_bounds__(kSelWG) void blk_write_plan_kernel(int n, int G, co
     total = block_sum_i64(total, red);
     const bool go = total > 0 && tn <= plan->t_limit;
     if (go) {
-        const int k0 = blockIdx.x * kBlkChunk + tid * kBlkPer;
+        const int per = ch / kSelWG;   // consecutive entries per lane
+        const int k0 = blockIdx.x * ch + tid * per;
         int cnt = 0;
-#pragma unroll
-        for (int u = 0; u < kBlkPer; ++u) {
+        for (int u = 0; u < per; ++u) {
             const int k = k0 + u;
             cnt += (k < n && t[k] + dt[k] == tn) ? 1 : 0;
         }
@@ -277,8 +296,7 @@ __global__ __launch_bounds__(kSelWG) void blk_write_plan_kernel(int n, int G, co
         int wbase = 0;
         for (int k = 0; k < w; ++k) wbase += wsum[k];
         int64_t pos = before + wbase + incl - cnt;
-#pragma unroll
-        for (int u = 0; u < kBlkPer; ++u) {
+        for (int u = 0; u < per; ++u) {
             const int k = k0 + u;
             if (k < n && t[k] + dt[k] == tn) idx[pos++] = k;
         }
@@ -303,24 +321,28 @@ __global__ __launch_bounds__(kSelWG) void blk_write_plan_kernel(int n, int G, co
     }
 }
 
-int blk_scratch_words(int n) { return 2 * ((n + kBlkChunk - 1) / kBlkChunk); }
+int blk_scratch_words(int n) {
+    const int ch = blk_chunk(n);
+    return 2 * ((n + ch - 1) / ch);
+}
 
 hipError_t launch_blk_front(const PackArgs& pa, const int64_t* dt, int32_t* idx, int64_t* sel2, DevPlan* plan,
                             int64_t* scratch, int per_blk, int tile_j, hipStream_t st) {
     const int n = pa.n;
     if (n <= 0) return hipErrorInvalidValue;
-    const int G = (n + kBlkChunk - 1) / kBlkChunk;
+    const int ch = blk_chunk(n);
+    const int G = (n + ch - 1) / ch;
     int64_t* gmin = scratch;
     int64_t* gcnt = scratch + G;
-    hipLaunchKernelGGL(select_min_kernel<kBlkChunk>, dim3(G), dim3(kSelWG), 0, st, n, pa.t, dt, gmin);
+    hipLaunchKernelGGL(blk_min_kernel, dim3(G), dim3(kSelWG), 0, st, n, ch, pa.t, dt, gmin);
     if (pa.prec == 0)
-        hipLaunchKernelGGL(blk_count_pack_kernel<0>, dim3(G), dim3(kSelWG), 0, st, G, dt, gmin, gcnt, sel2, plan,
-                           pa);
+        hipLaunchKernelGGL(blk_count_pack_kernel<0>, dim3(G), dim3(kSelWG), 0, st, ch, G, dt, gmin, gcnt, sel2,
+                           plan, pa);
     else
-        hipLaunchKernelGGL(blk_count_pack_kernel<1>, dim3(G), dim3(kSelWG), 0, st, G, dt, gmin, gcnt, sel2, plan,
-                           pa);
-    hipLaunchKernelGGL(blk_write_plan_kernel, dim3(G), dim3(kSelWG), 0, st, n, G, pa.t, dt, gcnt, sel2, idx, plan,
-                       per_blk, tile_j);
+        hipLaunchKernelGGL(blk_count_pack_kernel<1>, dim3(G), dim3(kSelWG), 0, st, ch, G, dt, gmin, gcnt, sel2,
+                           plan, pa);
+    hipLaunchKernelGGL(blk_write_plan_kernel, dim3(G), dim3(kSelWG), 0, st, n, ch, G, pa.t, dt, gcnt, sel2, idx,
+                       plan, per_blk, tile_j);
     return hipGetLastError();
 }
 
