@@ -897,9 +897,9 @@ static int hermite_enqueue_block(nbody_hermite* h, hipStream_t st) {
     r.G = h->o.G;
     for (int q = 0; q < 7; ++q) r.out[q] = h->f[q];
     r.plan = h->plan;
-    // 256 work-groups: 1024 waves for the wave-per-particle split reduce, 65536
-    // threads for the corrector alone; both stride over larger blocks
-    e = launch_blk_reduce_correct(r, correct_args(h, n), 256, st);
+    // 1024 work-groups: 4096 waves for the wave-per-particle split reduce,
+    // 262144 threads for the corrector alone; both stride over larger blocks
+    e = launch_blk_reduce_correct(r, correct_args(h, n), 1024, st);
     if (e != hipSuccess) return hip_err(c, e, "reduce/corrector launch");
     return NBODY_OK;
 }
