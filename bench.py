@@ -223,11 +223,11 @@ def kinds_timing(ctx, X, V, M, eps, prec, full_kernel_ms, reps=2):
     return out
 
 
-def block_run(n, t_end, precs, report_every=0.0):
+def block_run(n, t_end, precs, report_every=0.0, ctx=None, marks_out=True):
     """Hermite block steps on the Salpeter workload (Plummer positions and
     velocities, Salpeter masses 0.1-100 normalised to 1, eps = 1e-3,
-    Aarseth eta = 0.02, levels 2^-3 .. 2^-20) from t = 0 to t_end, both
-    precisions; prints one JSON line."""
+    Aarseth eta = 0.02, levels 2^-3 .. 2^-20) from t = 0 to t_end in the
+    given precisions; returns the result dict."""
     import torch
     import nbody_inputs as ics
     import paper_0707_0438_amd as nb
@@ -235,7 +235,9 @@ def block_run(n, t_end, precs, report_every=0.0):
     X = torch.from_numpy(p.pos).to("cuda")
     V = torch.from_numpy(p.vel).to("cuda")
     M = torch.from_numpy(p.mass).to("cuda")
-    ctx = nb.Context(0)
+    own = ctx is None
+    if own:
+        ctx = nb.Context(0)
     T = int(round(t_end * (1 << 20)))
     out = {"workload": f"salpeter_block: N={n} Plummer, Salpeter masses [0.1, 100] (sum 1), eps=1e-3, "
                        f"eta=0.02, block levels 2^-3..2^-20, t = 0 -> {t_end}",
@@ -270,11 +272,13 @@ def block_run(n, t_end, precs, report_every=0.0):
             "E0": e0, "E1": e1, "dE_over_E": (e1 - e0) / e0,
             "drift_per_time_unit": abs((e1 - e0) / e0) / max(st["t_ticks"] / (1 << 20), 1e-30),
             "us_per_block_step": round(wall / max(st["steps"], 1) * 1e6, 2),
-            "marks": marks,
         }
+        if marks_out:
+            out["runs"][prec]["marks"] = marks
         h.close()
-    ctx.close()
-    print(json.dumps(out), flush=True)
+    if own:
+        ctx.close()
+    return out
 
 
 def copy_calibration(nbytes=1 << 30, reps=4):
@@ -309,15 +313,16 @@ def main():
     ap.add_argument("--block-run", action="store_true",
                     help="only run the Salpeter block-step workload (--n, --t-end) and print its JSON")
     ap.add_argument("--t-end", type=float, default=1.0)
-    ap.add_argument("--extras", default="batched,adjoint,kinds",
-                    help="comma list of extra measurements (batched, adjoint, kinds) or 'none'")
+    ap.add_argument("--extras", default="batched,adjoint,kinds,block",
+                    help="comma list of extra measurements (batched, adjoint, kinds, block) or 'none'")
     ap.add_argument("--report-every", type=float, default=0.0)
     args = ap.parse_args()
     if args.copy_calibration:
         copy_calibration()
         return
     if args.block_run:
-        block_run(args.n if args.n != (1 << 20) else 65536, args.t_end, ["fp32", "ds"], args.report_every)
+        out = block_run(args.n if args.n != (1 << 20) else 65536, args.t_end, ["fp32", "ds"], args.report_every)
+        print(json.dumps(out), flush=True)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -414,6 +419,9 @@ def main():
     if "kinds" in extras:
         log("[bench] force-only and nearest-neighbour evaluations")
         line["kinds"] = kinds_timing(ctx, X, V, M, eps, args.prec, k_ms)
+    if "block" in extras:
+        log("[bench] block steps, Salpeter N=65536 to t=1/4")
+        line["block_steps"] = block_run(65536, 0.25, [args.prec], ctx=ctx, marks_out=False)
     if args.cpu_budget > 0:
         log("[bench] cpu baseline (oracle)")
         line["cpu_baseline"] = cpu_baseline(p, eps, args.cpu_budget)
