@@ -187,3 +187,47 @@ def test_block_steps_unsoftened_kepler(ctx):
           flush=True)
     assert np.abs(s["x"] - ref.x).max() < 1e-6
     assert abs(st["steps"] - ref.steps) <= max(2, ref.steps // 20)
+
+
+def test_salpeter64k_full_size_short_interval(ctx):
+    """The block-step workload at full size (N = 65536, Salpeter masses,
+    eps = 1e-3, eta = 0.02, levels 2^-3..2^-20) through the same driver the
+    benchmark times, t = 0 -> 1/512: in lockstep with the oracle until the
+    first block whose active set differs, then both to the end; block
+    structure, positions and energy compared."""
+    p = ics.workload("salpeter64k_block")
+    eps = 1e-3
+    t_end = TICKS // 512
+    ref = oracle.HermiteState(p.pos, p.vel, p.mass)
+    oracle.hermite_run(ref, 0, eps=eps, eta=0.02, init=True)
+    h = ctx.hermite(p.n, eps=eps, eta=0.02, dt_min_log2=-20, dt_max_log2=-3, prec="ds")
+    h.set_state(dev(p.pos), dev(p.vel), dev(p.mass))
+    e0 = sum(h.energy())
+    s0 = gpu_state(h)
+    assert np.mean(s0["dt"] == ref.dt) > 0.999
+    first_diff, k = None, 0
+    while True:
+        idx_ref, tn_ref = oracle.select_active(ref.t, ref.dt)
+        if tn_ref > t_end:
+            break
+        na, tt = h.step()
+        oracle.hermite_run(ref, tn_ref, eps=eps, eta=0.02, max_steps=1)
+        if tt != tn_ref or na != idx_ref.size:
+            first_diff = k
+            break
+        k += 1
+    st = h.advance(t_end)
+    oracle.hermite_run(ref, t_end, eps=eps, eta=0.02)
+    s = gpu_state(h)
+    dx = np.sort(np.abs(s["x"] - ref.x).max(axis=0))
+    print("salpeter64k to t=1/512: lockstep blocks", k, "first differing", first_diff, "steps gpu", st["steps"],
+          "oracle", ref.steps, "|dx| p99", dx[int(0.99 * dx.size)], "max", dx[-1], flush=True)
+    assert np.all(s["t"] <= t_end) and np.all(s["t"] % s["dt"] == 0)
+    assert abs(st["steps"] - ref.steps) <= max(2, ref.steps // 20)
+    if first_diff is None:
+        assert st["steps"] == ref.steps and st["sum_active"] == ref.sum_active
+        assert np.array_equal(s["t"], ref.t) and np.array_equal(s["dt"], ref.dt)
+    assert dx[int(0.99 * dx.size)] < 1e-9
+    ek, ep = h.energy()
+    print("salpeter64k energy drift gpu", abs((ek + ep - e0) / e0), flush=True)
+    assert abs((ek + ep - e0) / e0) < 1e-6
