@@ -421,7 +421,7 @@ def main():
         line["kinds"] = kinds_timing(ctx, X, V, M, eps, args.prec, k_ms)
     if "block" in extras:
         log("[bench] block steps, Salpeter N=65536 to t=1/4")
-        line["block_steps"] = block_run(65536, 0.25, [args.prec], ctx=ctx, marks_out=False)
+        line["block_steps"] = block_run(65536, 0.25, ["ds", "fp32"], ctx=ctx, marks_out=False)
     if args.cpu_budget > 0:
         log("[bench] cpu baseline (oracle)")
         line["cpu_baseline"] = cpu_baseline(p, eps, args.cpu_budget)
