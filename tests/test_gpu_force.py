@@ -180,3 +180,34 @@ def test_small_blocks_many_splits(ctx, prec):
                              i_self=dev(sel.astype(np.int32)))
         torch.cuda.synchronize()
         check((host(a), host(j), host(pt)), ref, prec, f"ni={ni} split={tile['split']}")
+
+
+def test_large_j_set(ctx):
+    """A j set of 2^25 + 77 particles (beyond 2^24, so record offsets and j
+    indices need more than float or 24-bit range) against 42 i-particles,
+    37 of them members of the set (including the last one) and 5 outside:
+    force in both precisions and the nearest neighbour against the oracle."""
+    import torch
+    nj = (1 << 25) + 77
+    g = np.random.default_rng(11)
+    xj = g.normal(size=(3, nj)); vj = 0.3 * g.normal(size=(3, nj)); mj = np.full(nj, 1.0 / nj)
+    members = np.sort(np.concatenate([g.choice(nj - 1, 36, replace=False), [nj - 1]]))
+    outside = g.normal(size=(3, 5)); vout = g.normal(size=(3, 5))
+    xi = np.concatenate([xj[:, members], outside], 1); vi = np.concatenate([vj[:, members], vout], 1)
+    iself = np.concatenate([members, -np.ones(5, dtype=np.int64)])
+    eps = 1e-3
+    ref = oracle.force(xi, vi, xj, vj, mj, eps, iself=iself)
+    ref_nn, _ = oracle.nearest(xi, xj, iself=iself)
+    X, V, M = dev(xj), dev(vj), dev(mj)
+    S = dev(iself.astype(np.int32))
+    for prec in ("ds", "fp32"):
+        a, j, pt = ctx.force(dev(xi), dev(vi), X, V, M, eps, prec=prec, i_self=S)
+        torch.cuda.synchronize()
+        check((host(a), host(j), host(pt)), ref, prec, "nj=2^25+77")
+    _, _, _, nn, _ = ctx.force_nn(dev(xi), dev(vi), X, V, M, eps, prec="ds", i_self=S)
+    torch.cuda.synchronize()
+    nn = host(nn)
+    d = ((xj[:, nn] - xi) ** 2).sum(0)
+    dref = ((xj[:, ref_nn] - xi) ** 2).sum(0)
+    assert np.all(d <= dref * (1 + 2e-6))
+    assert np.mean(nn == ref_nn) > 0.95
