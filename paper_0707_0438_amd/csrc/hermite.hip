@@ -447,17 +447,41 @@ __global__ __launch_bounds__(256) void blk_reduce_correct_kernel(ReduceArgs r, C
     const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
     for (int64_t w = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; w < n; w += nw) {
         const int c = (int)w;
-        double f[6];
+        // the six quantities' loads of two ranges are in flight together; each
+        // quantity still sums its ranges s = lane, lane + 64, ... in order
+        double f[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        const float2* col = r.part + c;
+        const size_t qs = (size_t)n, rs = 7 * (size_t)n;
+        int sp = lane;
+        for (; sp + 64 < S; sp += 128) {
+            float2 u[6], v[6];
+#pragma unroll
+            for (int q = 0; q < 6; ++q) {
+                u[q] = col[(size_t)sp * rs + q * qs];
+                v[q] = col[(size_t)(sp + 64) * rs + q * qs];
+            }
+#pragma unroll
+            for (int q = 0; q < 6; ++q) {
+                f[q] += (double)u[q].x;
+                f[q] += (double)u[q].y;
+                f[q] += (double)v[q].x;
+                f[q] += (double)v[q].y;
+            }
+        }
+        if (sp < S) {
+            float2 u[6];
+#pragma unroll
+            for (int q = 0; q < 6; ++q) u[q] = col[(size_t)sp * rs + q * qs];
+#pragma unroll
+            for (int q = 0; q < 6; ++q) {
+                f[q] += (double)u[q].x;
+                f[q] += (double)u[q].y;
+            }
+        }
 #pragma unroll
         for (int q = 0; q < 6; ++q) {
-            double s = 0.0;
-            for (int sp = lane; sp < S; sp += 64) {
-                const float2 p = r.part[((size_t)sp * 7 + q) * n + c];
-                s += (double)p.x;
-                s += (double)p.y;
-            }
-            for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
-            f[q] = r.G * s;
+            for (int off = 32; off > 0; off >>= 1) f[q] += __shfl_xor(f[q], off);
+            f[q] = r.G * f[q];
         }
         if (lane == 0) correct_core(ca, c, f, f + 3);
     }
