@@ -375,7 +375,7 @@ int nbody_destroy(nbody_ctx* c) {
         if (c->gstream) (void)hipStreamDestroy(c->gstream);
         DevBuf* bufs[] = {&c->ipack, &c->jpack, &c->part, &c->sel, &c->scratch64,
                           &c->vrec_i, &c->vrec_j, &c->vpart, &c->integ, &c->hist, &c->bplan,
-                          &c->bstate};
+                          &c->bstate, &c->lf};
         for (DevBuf* b : bufs)
             if (b->p) (void)hipFree(b->p);
     }
