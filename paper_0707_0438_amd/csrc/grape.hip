@@ -370,11 +370,18 @@ int GPUcalc_firsthalf(int clusterid, int nj, int ni, const int index[], const do
     const int32_t* self = nj > 0 ? s.dint : nullptr;
     rc = s.nn ? nbody_force_nn(s.ctx, s.st, prec, 1.0, eps, ni, I, self, nj, J, O, s.dint + ic, nullptr)
               : nbody_force(s.ctx, s.st, prec, 1.0, eps, ni, I, self, nj, J, O);
-    if (rc) return lib_fail(s, rc, "force calculation");
+    if (rc) {
+        // the i upload may still be reading the pinned rows the next call writes
+        (void)hipStreamSynchronize(s.st);
+        return lib_fail(s, rc, "force calculation");
+    }
     e = hipMemcpyAsync(s.pin + 6 * ic, o, sizeof(double) * 7 * ic, hipMemcpyDeviceToHost, s.st);
     if (e == hipSuccess && s.nn)
         e = hipMemcpyAsync(s.pint + ic, s.dint + ic, sizeof(int32_t) * ni, hipMemcpyDeviceToHost, s.st);
-    if (e != hipSuccess) return hip_fail(s, e, "result download");
+    if (e != hipSuccess) {
+        (void)hipStreamSynchronize(s.st);
+        return hip_fail(s, e, "result download");
+    }
     s.pending = true;
     return NBODY_OK;
 }
