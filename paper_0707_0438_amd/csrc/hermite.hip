@@ -216,6 +216,9 @@ hipError_t launch_select(int n, const int64_t* t, const int64_t* dt, int32_t* id
 // A step whose t_next lies beyond the plan's end time changes nothing and
 // marks the plan frozen.  Integer selection, so the block is exact.
 constexpr int kBlkGroups = 256;
+// Block steps split j down to this many tiles per range: small blocks are
+// latency-bound, so short j-ranges on many work-groups finish sooner.
+constexpr int kBlkMinTiles = 2;
 
 __host__ __device__ inline int blk_chunk(int n) {
     int ch = kSelWG;
@@ -308,7 +311,7 @@ __global__ __launch_bounds__(kSelWG) void blk_write_plan_kernel(int n, int ch, i
             plan->frozen = 1;
         } else {
             int nb, S, jc;
-            split_plan(total, n, per_blk, tile_j, 0, &nb, &S, &jc);
+            split_plan(total, n, per_blk, tile_j, 0, &nb, &S, &jc, kBlkMinTiles);
             plan->n_act = total;
             plan->t_next = tn;
             plan->nb = nb;

@@ -23,10 +23,10 @@ inline int rec_words(int prec) { return prec == 0 ? kRecFP32 : kRecDS; }
 // Launch geometry of the pairwise kernel for an i-list of ni against nj:
 // nb i-blocks of per_blk particles and S j-ranges of jchunk records (a
 // multiple of the tile).  Enough work-groups to cover the 256 CUs several
-// times, with at least 4 tiles per j-range.  Used by the host for direct
+// times, with at least min_tiles tiles per j-range.  Used by the host for direct
 // calls and by the device for block steps whose size only it knows.
 __host__ __device__ inline void split_plan(int64_t ni, int64_t nj, int per_blk, int tile_j, int split_req,
-                                           int* nb_out, int* S_out, int* jchunk_out) {
+                                           int* nb_out, int* S_out, int* jchunk_out, int min_tiles = 4) {
     const int64_t nb = (ni + per_blk - 1) / per_blk;
     int64_t S = split_req;
     if (S <= 0) {
@@ -35,7 +35,7 @@ __host__ __device__ inline void split_plan(int64_t ni, int64_t nj, int per_blk, 
             S = 1;
         } else {
             S = (target + nb - 1) / nb;
-            int64_t smax = nj / (4 * (int64_t)tile_j);
+            int64_t smax = nj / ((int64_t)min_tiles * tile_j);
             if (smax < 1) smax = 1;
             if (S > smax) S = smax;
             if (S < 1) S = 1;
