@@ -148,11 +148,13 @@ def test_force_nn_exact_ties_take_lowest_index(ctx, prec):
     X, V, M = dev(pos), dev(vel), dev(m)
     for sel in (np.arange(n), np.sort(g.choice(n, 60, replace=False))):
         ref_nn, ref_r2 = oracle.nearest(pos[:, sel], pos, iself=sel)
-        _, _, _, nn, r2 = ctx.force_nn(X[:, sel].contiguous(), V[:, sel].contiguous(), X, V, M, 0.1, prec=prec,
-                                       i_self=dev(sel.astype(np.int32)))
-        torch.cuda.synchronize()
-        assert np.array_equal(host(nn), ref_nn)
-        assert np.array_equal(host(r2), ref_r2)
+        for eps in (0.1, 0.0):   # the softened and the unsoftened (eps = 0) kernels
+            a, _, pt, nn, r2 = ctx.force_nn(X[:, sel].contiguous(), V[:, sel].contiguous(), X, V, M, eps,
+                                            prec=prec, i_self=dev(sel.astype(np.int32)))
+            torch.cuda.synchronize()
+            assert np.array_equal(host(nn), ref_nn), eps
+            assert np.array_equal(host(r2), ref_r2), eps
+            assert np.all(np.isfinite(host(a))) and np.all(np.isfinite(host(pt)))
 
 
 def test_force_nn_degenerate(ctx):
