@@ -231,3 +231,23 @@ def test_salpeter64k_full_size_short_interval(ctx):
     ek, ep = h.energy()
     print("salpeter64k energy drift gpu", abs((ek + ep - e0) / e0), flush=True)
     assert abs((ek + ep - e0) / e0) < 1e-6
+
+
+@pytest.mark.parametrize("prec", ["ds", "fp32"])
+def test_shared_steps_unsoftened_kepler(ctx, prec):
+    """The e = 0.5 two-body orbit with eps = 0 and shared steps of 2^-8 to
+    t = 1/2 (the unsoftened kernel through the shared-step driver) against
+    the oracle."""
+    from test_oracle_hermite import kepler_state
+    m = np.array([0.6, 0.4])
+    x0, v0 = kepler_state(0.6, 0.4, 1.0, 0.5, 0.0)
+    ref = oracle.HermiteState(x0, v0, m)
+    oracle.hermite_run(ref, TICKS // 2, eps=0.0, shared_log2=-8, init=True)
+    h = ctx.hermite(2, eps=0.0, shared_dt_log2=-8, prec=prec)
+    h.set_state(dev(x0), dev(v0), dev(m))
+    st = h.advance(TICKS // 2)
+    s = gpu_state(h)
+    assert st["steps"] == 128 and np.all(s["t"] == TICKS // 2)
+    dx = np.abs(s["x"] - ref.x).max()
+    print(prec, "kepler shared max|dx|", dx, flush=True)
+    assert dx < (1e-6 if prec == "ds" else 1e-4)
