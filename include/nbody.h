@@ -164,7 +164,11 @@ int nbody_autotune(nbody_ctx *ctx, hipStream_t stream, nbody_prec prec, double G
  * kernel visits every j, including j = i_self[i]; that pair contributes
  * exactly zero to a and jerk because its rows are bit-identical, and its
  * potential term is removed after the loop (Section 3.1).  The caller must
- * therefore pass, for a self pair, an i row equal to the j row.
+ * therefore pass, for a self pair, an i row equal to the j row.  With the
+ * environment variable NBODY_DEBUG_SELF_CHECK=1 set when the context is
+ * created, the call verifies this on the packed rows (and that every
+ * i_self < n_j), synchronising the stream, and returns NBODY_ERR_ARG when a
+ * row differs.
  * I.m is unused.  Returns NBODY_ERR_ARG for NULL rows, n_i < 0, n_j < 0,
  * counts above 2^31 - 1, non-finite G or eps, eps < 0. */
 int nbody_force(nbody_ctx *ctx, hipStream_t stream, nbody_prec prec, double G, double eps,

@@ -44,6 +44,7 @@ struct nbody_ctx {
     nb::TuneCache tune;
     int alloc_count = 0;
     int fail_alloc_at = 0;    // debug: NBODY_DEBUG_FAIL_ALLOC=k fails the k-th allocation
+    bool self_check = false;  // debug: NBODY_DEBUG_SELF_CHECK=1 verifies self rows (synchronises)
     // kernel timing: event pairs recorded around each pairwise-kernel launch
     bool timing = false;
     std::vector<hipEvent_t> ev;   // 2 per launch
@@ -328,6 +329,23 @@ static bool same_src(const nbody_src& a, const nbody_src& b) {
     return a.x == b.x && a.y == b.y && a.z == b.z && a.vx == b.vx && a.vy == b.vy && a.vz == b.vz;
 }
 
+// Debug mode (NBODY_DEBUG_SELF_CHECK=1): the packed i rows named by i_self
+// must equal their j rows bit for bit; synchronises `st`.
+static int debug_self_check(nbody_ctx* c, hipStream_t st, int prec, int64_t ni, const float4* ip,
+                            const int32_t* iself, int64_t nj, const float4* jp) {
+    if (!c->self_check || !iself || ni == 0) return NBODY_OK;
+    int rc = dev_alloc(c, c->scratch64, sizeof(int64_t));
+    if (rc) return rc;
+    int* bad = (int*)c->scratch64.p;
+    hipError_t e = launch_self_check((int)ni, (int)nj, prec, ip, iself, jp, bad, st);
+    int h = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&h, bad, sizeof(int), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_err(c, e, "self check");
+    if (h) return set_err(c, NBODY_ERR_ARG, "i_self: %d i rows differ from their j rows or index beyond n_j", h);
+    return NBODY_OK;
+}
+
 extern "C" {
 
 int nbody_abi_version(void) { return NBODY_ABI_VERSION; }
@@ -339,6 +357,7 @@ int nbody_create(nbody_ctx** ctx, int device, const char* tune_cache_path) {
     nbody_ctx* c = new (std::nothrow) nbody_ctx();
     if (!c) return NBODY_ERR_NOMEM;
     if (const char* f = getenv("NBODY_DEBUG_FAIL_ALLOC")) c->fail_alloc_at = atoi(f);
+    if (const char* f = getenv("NBODY_DEBUG_SELF_CHECK")) c->self_check = atoi(f) != 0;
     const char* path = tune_cache_path ? tune_cache_path : getenv("NBODY_TUNE_CACHE");
     if (path && *path) c->tune.set_path(path);
     if (device >= 0) {
@@ -500,6 +519,7 @@ int nbody_force(nbody_ctx* c, hipStream_t st, nbody_prec prec, double G, double 
         if (rc) return rc;
         ip = (const float4*)c->ipack.p;
     }
+    if ((rc = debug_self_check(c, st, p, n_i, ip, i_self, n_j, (const float4*)c->jpack.p))) return rc;
     double* o[7] = {out.ax, out.ay, out.az, out.jx, out.jy, out.jz, out.pot};
     return run_force(c, st, p, G, eps, n_i, ip, nullptr, i_self, 0, n_j, (const float4*)c->jpack.p, o,
                      nullptr);
@@ -542,6 +562,7 @@ static int force_kind(nbody_ctx* c, hipStream_t st, nbody_prec prec, double G, d
         if (rc) return rc;
         ip = (const float4*)c->ipack.p;
     }
+    if ((rc = debug_self_check(c, st, p, n_i, ip, i_self, n_j, (const float4*)c->jpack.p))) return rc;
     double* o[7] = {out.ax, out.ay, out.az, vel ? out.jx : nullptr, vel ? out.jy : nullptr,
                     vel ? out.jz : nullptr, out.pot};
     return run_force(c, st, p, G, eps, n_i, ip, nullptr, i_self, 0, n_j, (const float4*)c->jpack.p, o, nullptr,

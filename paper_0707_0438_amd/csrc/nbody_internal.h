@@ -154,6 +154,10 @@ struct PackArgs {
     const int64_t* gate;                           // device scalar; 0 = skip (or NULL)
 };
 hipError_t launch_pack(const PackArgs& a, hipStream_t st);
+// Debug: *bad = number of i rows whose self index names a j record that is
+// not bit-identical in position and velocity (or lies beyond nj).
+hipError_t launch_self_check(int ni, int nj, int prec, const float4* ip, const int32_t* iself, const float4* jp,
+                             int* bad, hipStream_t st);
 
 // Active-block selection: out2[0] = n_act, out2[1] = t_next.  scratch: device
 // int64 words, at least select_scratch_words(n).

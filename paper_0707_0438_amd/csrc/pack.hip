@@ -58,4 +58,33 @@ hipError_t launch_predict_all(int n, const double* const* s, const int64_t* t, c
     return hipGetLastError();
 }
 
+// Debug check of the self-pair contract: for every i with a self index s,
+// the i record's position and velocity words must equal those of j record s
+// bit for bit (the tile loop visits the pair and relies on it giving exactly
+// zero).  Counts offending rows, and self indices beyond the j set.
+__global__ __launch_bounds__(256) void self_check_kernel(int ni, int nj, int R, const float4* __restrict__ ip,
+                                                         const int32_t* __restrict__ iself,
+                                                         const float4* __restrict__ jp, int* __restrict__ bad) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ni) return;
+    const int s = iself[i];
+    if (s < 0) return;
+    bool ok = s < nj;
+    for (int r = 0; ok && r < R; ++r) {
+        const float4 a = ip[(size_t)i * R + r], b = jp[(size_t)s * R + r];
+        ok = __float_as_uint(a.x) == __float_as_uint(b.x) && __float_as_uint(a.y) == __float_as_uint(b.y) &&
+             __float_as_uint(a.z) == __float_as_uint(b.z);
+    }
+    if (!ok) atomicAdd(bad, 1);
+}
+
+hipError_t launch_self_check(int ni, int nj, int prec, const float4* ip, const int32_t* iself, const float4* jp,
+                             int* bad, hipStream_t st) {
+    hipError_t e = launch_fill_i32(bad, 1, 0, st);
+    if (e != hipSuccess || ni <= 0) return e;
+    hipLaunchKernelGGL(self_check_kernel, dim3((ni + 255) / 256), dim3(256), 0, st, ni, nj,
+                       prec == 0 ? kRecFP32 : kRecDS, ip, iself, jp, bad);
+    return hipGetLastError();
+}
+
 }  // namespace nb

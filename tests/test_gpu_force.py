@@ -211,3 +211,36 @@ def test_large_j_set(ctx):
     dref = ((xj[:, ref_nn] - xi) ** 2).sum(0)
     assert np.all(d <= dref * (1 + 2e-6))
     assert np.mean(nn == ref_nn) > 0.95
+
+
+def test_debug_self_check(monkeypatch):
+    """With NBODY_DEBUG_SELF_CHECK=1 the library verifies that every i row
+    named by i_self equals its j row bit for bit (and lies in the j set)."""
+    import torch
+    import paper_0707_0438_amd as nb
+    monkeypatch.setenv("NBODY_DEBUG_SELF_CHECK", "1")
+    c = nb.Context(0)
+    try:
+        p = ics.plummer(300, 108)
+        X, V, M = dev(p.pos), dev(p.vel), dev(p.mass)
+        sel = np.arange(0, 300, 7)
+        XI, VI = X[:, sel].contiguous(), V[:, sel].contiguous()
+        S = dev(sel.astype(np.int32))
+        for prec in ("ds", "fp32"):
+            c.force(XI, VI, X, V, M, 0.01, prec=prec, i_self=S)
+            c.force_acc(XI, X, M, 0.01, prec=prec, i_self=S)
+        torch.cuda.synchronize()
+        XI[0, 3] += 1e-3                    # i row 3 no longer equals j row 21
+        with pytest.raises(nb.NBodyError, match="i_self"):
+            c.force(XI, VI, X, V, M, 0.01, i_self=S)
+        with pytest.raises(nb.NBodyError, match="i_self"):
+            c.force_acc(XI, X, M, 0.01, prec="fp32", i_self=S)
+        XI[0, 3] -= 1e-3
+        XI[0, 3] = X[0, sel[3]]
+        bad = S.clone()
+        bad[1] = 5000                       # beyond the j set
+        with pytest.raises(nb.NBodyError, match="i_self"):
+            c.force(XI, VI, X, V, M, 0.01, i_self=bad)
+        c.force(XI, VI, X, V, M, 0.01, i_self=S)
+    finally:
+        c.close()
