@@ -235,8 +235,7 @@ def test_debug_self_check(monkeypatch):
             c.force(XI, VI, X, V, M, 0.01, i_self=S)
         with pytest.raises(nb.NBodyError, match="i_self"):
             c.force_acc(XI, X, M, 0.01, prec="fp32", i_self=S)
-        XI[0, 3] -= 1e-3
-        XI[0, 3] = X[0, sel[3]]
+        XI[0, 3] = X[0, sel[3]]             # restored
         bad = S.clone()
         bad[1] = 5000                       # beyond the j set
         with pytest.raises(nb.NBodyError, match="i_self"):
