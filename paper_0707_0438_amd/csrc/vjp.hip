@@ -142,7 +142,9 @@ __global__ __launch_bounds__(kVjpWG) void vjp_kernel(VjpArgs a) {
         }
     };
 
-    const float eps2 = a.eps2;
+    // eps^2 in a VGPR: an SGPR operand halves the issue rate of its instruction
+    float eps2;
+    asm volatile("v_mov_b32 %0, %1" : "=v"(eps2) : "s"(a.eps2));
     if (ntiles > 0) {
         load_tile(0);
         store_tile(0);
