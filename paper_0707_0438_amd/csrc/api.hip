@@ -799,7 +799,7 @@ static int plan_read(nbody_hermite* h, hipStream_t st, DevPlan* p) {
     return NBODY_OK;
 }
 
-static int pack_predicted(nbody_hermite* h, hipStream_t st, const int64_t* gate) {
+static int pack_predicted(nbody_hermite* h, hipStream_t st, int64_t tn) {
     nbody_ctx* c = h->ctx;
     const int p = (int)h->o.prec;
     const int n = (int)h->n;
@@ -814,9 +814,9 @@ static int pack_predicted(nbody_hermite* h, hipStream_t st, const int64_t* gate)
     pa.ax = h->s[6]; pa.ay = h->s[7]; pa.az = h->s[8];
     pa.jx = h->s[9]; pa.jy = h->s[10]; pa.jz = h->s[11];
     pa.t = h->t;
-    pa.tnext = h->sel2 + 1;
+    pa.tnext = nullptr;
+    pa.tn = tn;
     pa.out = (float4*)c->jpack.p;
-    pa.gate = gate;
     hipError_t e = launch_pack(pa, st);
     if (e != hipSuccess) return hip_err(c, e, "predict/pack launch");
     return NBODY_OK;
@@ -843,24 +843,25 @@ static CorrectArgs correct_args(nbody_hermite* h, int n_act) {
 }
 
 // Shared steps: every particle is due every step, so the block (all n, in
-// order) and its time are known on the host; no readback.
+// order) and its time are known on the host: no selection pass, the block
+// time goes to the kernels by value, and the i-list is the identity.
 static int hermite_step_shared(nbody_hermite* h, hipStream_t st, int64_t t_limit, bool* stopped) {
     nbody_ctx* c = h->ctx;
     const int n = (int)h->n;
     const int64_t tn = h->t_ticks + ((int64_t)1 << (h->o.shared_dt_log2 + 20));
     *stopped = tn > t_limit;
     if (*stopped) return NBODY_OK;
-    int rc = dev_alloc(c, c->sel, (2 + (size_t)select_scratch_words(n)) * sizeof(int64_t));
-    if (rc) return rc;
-    hipError_t e = launch_select(n, h->t, h->dt, h->idx, h->sel2, (int64_t*)c->sel.p + 2, st);
-    if (e != hipSuccess) return hip_err(c, e, "select launch");
-    rc = pack_predicted(h, st, nullptr);
+    int rc = pack_predicted(h, st, tn);
     if (rc) return rc;
     const int p = (int)h->o.prec;
-    rc = run_force(c, st, p, h->o.G, h->o.eps, n, (const float4*)c->jpack.p, h->idx, nullptr, 1, n,
+    rc = run_force(c, st, p, h->o.G, h->o.eps, n, (const float4*)c->jpack.p, nullptr, nullptr, 2, n,
                    (const float4*)c->jpack.p, h->f, nullptr);
     if (rc) return rc;
-    e = launch_correct(correct_args(h, n), st);
+    CorrectArgs ca = correct_args(h, n);
+    ca.idx = nullptr;
+    ca.tnext = nullptr;
+    ca.tn = tn;
+    hipError_t e = launch_correct(ca, st);
     if (e != hipSuccess) return hip_err(c, e, "corrector launch");
     h->t_ticks = tn;
     h->steps += 1;

@@ -377,8 +377,8 @@ __global__ __launch_bounds__(256) void correct_kernel(CorrectArgs a) {
 
 __device__ __forceinline__ void correct_core(const CorrectArgs& a, int c, const double* a1in,
                                              const double* j1in) {
-    const int i = a.idx[c];
-    const int64_t tn = *a.tnext;
+    const int i = a.idx ? a.idx[c] : c;
+    const int64_t tn = a.tnext ? *a.tnext : a.tn;
     if (c == 0 && a.tnow) *a.tnow = tn;
     const double D = (double)a.dt[i] * kTick;
     double* X[3] = {a.x, a.y, a.z};

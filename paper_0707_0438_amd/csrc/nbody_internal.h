@@ -149,9 +149,9 @@ struct PackArgs {
     const double *x, *y, *z, *vx, *vy, *vz, *m;
     const double *ax, *ay, *az, *jx, *jy, *jz;   // predictor inputs (or NULL)
     const int64_t* t;                              // ticks (or NULL: no prediction)
-    const int64_t* tnext;                          // device scalar
+    const int64_t* tnext;                          // device scalar (NULL: use tn)
+    int64_t tn;                                    // block time when tnext is NULL
     float4* out;
-    const int64_t* gate;                           // device scalar; 0 = skip (or NULL)
 };
 hipError_t launch_pack(const PackArgs& a, hipStream_t st);
 // Debug: *bad = number of i rows whose self index names a j record that is
@@ -167,8 +167,9 @@ hipError_t launch_select(int n, const int64_t* t, const int64_t* dt, int32_t* id
 
 struct CorrectArgs {
     int n_act;
-    const int32_t* idx;
-    const int64_t* tnext;             // device scalar
+    const int32_t* idx;               // block list (NULL: particles 0 .. n_act-1)
+    const int64_t* tnext;             // device scalar (NULL: use tn)
+    int64_t tn;                       // block time when tnext is NULL
     double *x, *y, *z, *vx, *vy, *vz;
     double *ax, *ay, *az, *jx, *jy, *jz;
     int64_t *t, *dt;

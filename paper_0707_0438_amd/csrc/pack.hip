@@ -11,8 +11,7 @@ template <int PREC>
 __global__ __launch_bounds__(256) void pack_kernel(PackArgs a) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= a.n) return;
-    if (a.gate && *a.gate == 0) return;
-    pack_one<PREC>(a, k, a.t ? *a.tnext : 0);
+    pack_one<PREC>(a, k, a.t ? (a.tnext ? *a.tnext : a.tn) : 0);
 }
 
 hipError_t launch_pack(const PackArgs& a, hipStream_t st) {
