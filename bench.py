@@ -57,6 +57,17 @@ def traffic_per_launch(prec: str):
         return None
 
 
+def device_info():
+    """What the runtime reports about the GPU, and how the FP32 peak used for
+    the roofline is derived."""
+    import torch
+    pr = torch.cuda.get_device_properties(0)
+    return {"name": pr.name, "arch": getattr(pr, "gcnArchName", ""), "compute_units": pr.multi_processor_count,
+            "memory_GiB": round(pr.total_memory / 2 ** 30, 1),
+            "fp32_peak": f"{pr.multi_processor_count} CU x 64 lanes x 2 (dual issue) x 2 (FMA) x 2.4 GHz "
+                         f"= {pr.multi_processor_count * 64 * 2 * 2 * 2.4e9 / 1e12:.1f} TFLOP/s"}
+
+
 def time_steps(ctx, h, steps, warmup):
     import torch
     for _ in range(warmup):
@@ -387,6 +398,7 @@ def main():
             "tile": r["tile"],
         },
         "pct_fp32_peak": round(100.0 * FLOPS_PER_INTERACTION * value * 1e9 / (FP32_PEAK_TFLOPS * 1e12), 2),
+        "device": device_info(),
         "roofline": {
             "bound": "alu",
             "achieved": round(achieved, 3),
