@@ -64,7 +64,7 @@ def device_info():
     pr = torch.cuda.get_device_properties(0)
     return {"name": pr.name, "arch": getattr(pr, "gcnArchName", ""), "compute_units": pr.multi_processor_count,
             "memory_GiB": round(pr.total_memory / 2 ** 30, 1),
-            "fp32_peak": f"{pr.multi_processor_count} CU x 64 lanes x 2 (dual issue) x 2 (FMA) x 2.4 GHz "
+            "fp32_peak": f"{pr.multi_processor_count} CU x 64 lanes x 2 (packed FP32 rate) x 2 (FMA) x 2.4 GHz "
                          f"= {pr.multi_processor_count * 64 * 2 * 2 * 2.4e9 / 1e12:.1f} TFLOP/s"}
 
 
