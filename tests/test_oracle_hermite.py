@@ -191,3 +191,36 @@ def test_shared_adjoint_translation_and_boost():
     gx0, gv0, _ = oracle.hermite_shared_adjoint(p.pos, p.vel, p.mass, eps, D, steps, w)
     np.testing.assert_allclose(gx0.sum(axis=1), w.sum(axis=1), rtol=1e-9, atol=1e-9)
     np.testing.assert_allclose(gv0.sum(axis=1), steps * D * w.sum(axis=1), rtol=1e-9, atol=1e-9)
+
+
+def test_aarseth_criterion_on_circular_orbit():
+    """On a circular orbit of angular frequency w every derivative of the
+    acceleration has magnitude |a| w^k and successive ones are orthogonal,
+    so the criterion sqrt(eta (|a||a2| + |j|^2) / (|j||a3| + |a2|^2))
+    reduces to sqrt(eta) / w whatever |a| is.  The second derivative is the
+    one carried to the new time, a2 + a3 D."""
+    g = np.random.default_rng(5)
+    for _ in range(20):
+        A, w, eta = g.uniform(0.1, 10), g.uniform(0.1, 10), g.uniform(0.001, 0.1)
+        ph = g.uniform(0, 2 * math.pi)
+        e1 = np.array([math.cos(ph), math.sin(ph), 0.0])
+        e2 = np.array([-math.sin(ph), math.cos(ph), 0.0])
+        a1, j1 = -A * e1, -A * w * e2
+        a2_new, a3 = A * w * w * e1, A * w ** 3 * e2
+        for D in (0.0, 1e-3, 0.25):
+            dt = oracle.aarseth_dt(a1, j1, a2_new - a3 * D, a3, D, eta)
+            assert dt == pytest.approx(math.sqrt(eta) / w, rel=1e-12), (A, w, eta, D)
+
+
+def test_first_step_on_circular_orbit():
+    """The first step eta_s |a| / |j| is 1 / w on a circular orbit (each
+    body's acceleration turns at the orbital frequency), so the initial level
+    is the largest power of two not above eta_s / w."""
+    for a, eta_s in ((1.0, 0.01), (0.3, 0.02), (2.5, 0.005)):
+        m = np.array([0.6, 0.4])
+        x0, v0 = kepler_state(0.6, 0.4, a, 0.0, 0.0)
+        w = math.sqrt(1.0 / a ** 3)
+        st = oracle.HermiteState(x0, v0, m)
+        oracle.hermite_run(st, 0, eps=0.0, eta_s=eta_s, init=True)
+        want = 2.0 ** math.floor(math.log2(eta_s / w))
+        assert np.all(st.dt == int(round(want / TICK))), (a, eta_s, st.dt)
