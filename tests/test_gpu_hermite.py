@@ -251,3 +251,23 @@ def test_shared_steps_unsoftened_kepler(ctx, prec):
     dx = np.abs(s["x"] - ref.x).max()
     print(prec, "kepler shared max|dx|", dx, flush=True)
     assert dx < (1e-6 if prec == "ds" else 1e-4)
+
+
+def test_single_particle_block_steps(ctx):
+    """One particle: no force, a step criterion of 0/0, hence the smallest
+    level (a zero or non-finite criterion gives 2^lmin); it drifts in a
+    straight line, step after step, with only kinetic energy."""
+    x0 = np.array([[0.25], [-0.5], [1.0]])
+    v0 = np.array([[0.125], [0.0], [-0.25]])
+    m = np.array([0.75])
+    h = ctx.hermite(1, eps=1e-2, eta=0.02, dt_min_log2=-12, dt_max_log2=-3, prec="ds")
+    h.set_state(dev(x0), dev(v0), dev(m))
+    for k in range(1, 4):
+        na, tt = h.step()
+        assert na == 1 and tt == k * (TICKS >> 12)
+    s = gpu_state(h)
+    assert np.all(s["dt"] == TICKS >> 12)
+    np.testing.assert_allclose(s["x"], x0 + v0 * 3 * 2.0 ** -12, rtol=0, atol=1e-15)
+    assert np.array_equal(s["v"], v0)
+    ek, ep = h.energy()
+    assert ek == pytest.approx(0.5 * 0.75 * (0.125 ** 2 + 0.25 ** 2), rel=1e-14) and ep == 0.0
