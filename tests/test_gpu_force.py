@@ -243,3 +243,42 @@ def test_debug_self_check(monkeypatch):
         c.force(XI, VI, X, V, M, 0.01, i_self=S)
     finally:
         c.close()
+
+
+def test_autotune_cache_timing_and_reserve(tmp_path):
+    """The autotuner picks a compiled shape, stores it in the JSON-lines cache
+    and a new context reading that cache uses it for the same size bucket;
+    results in the tuned shape still meet the bars; per-launch kernel timing
+    counts launches; nbody_reserve pre-sizes scratch."""
+    import json
+    import torch
+    import paper_0707_0438_amd as nb
+    cache = str(tmp_path / "tune.jsonl")
+    p = ics.plummer(3000, 109)
+    X, V, M = dev(p.pos), dev(p.vel), dev(p.mass)
+    c = nb.Context(0, tune_cache=cache)
+    try:
+        c.reserve(4096, 4096)
+        tile, ms = c.autotune(X, V, X, V, M, 0.01, prec="ds", reps=1)
+        assert ms > 0 and tile["tile_j"] in (64, 128, 256) and tile["ipt"] in (1, 2, 4)
+        lines = [json.loads(ln) for ln in open(cache) if ln.strip()]
+        assert len(lines) >= 1
+        got = c.get_tile(3000, 3000, "ds")
+        assert (got["tile_j"], got["ipt"], got["wg"]) == (tile["tile_j"], tile["ipt"], tile["wg"])
+        c.kernel_timing(True)
+        S = torch.arange(p.n, dtype=torch.int32, device="cuda")
+        for _ in range(3):
+            a, j, pt = c.force(X, V, X, V, M, 0.01, prec="ds", i_self=S)
+        kms, launches = c.kernel_time()
+        c.kernel_timing(False)
+        assert launches == 3 and kms > 0
+        ref = oracle.force(p.pos, p.vel, p.pos, p.vel, p.mass, 0.01, iself=np.arange(p.n))
+        check((host(a), host(j), host(pt)), ref, "ds", "tuned shape")
+    finally:
+        c.close()
+    c2 = nb.Context(0, tune_cache=cache)
+    try:
+        got = c2.get_tile(3000, 3000, "ds")
+        assert (got["tile_j"], got["ipt"], got["wg"]) == (tile["tile_j"], tile["ipt"], tile["wg"])
+    finally:
+        c2.close()
