@@ -139,3 +139,26 @@ def test_plummer16k_gradient_identities(ctx):
     print("translation", ex, "boost", ev, flush=True)
     assert ex < 1e-6 and ev < 1e-6
     assert np.all(np.isfinite(host(gm)))
+
+
+def test_plummer16k_gradient_against_oracle_adjoint(ctx):
+    """The full differentiation workload (N = 16384, eps = 1e-3, 64 steps of
+    1/128, checkpoints every 8, L = sum w.x(T)): every gradient component
+    against the float64 oracle's adjoint of the same run (the oracle adjoint
+    is pinned by central differences in the CPU tests).  About a minute of
+    host time for the oracle."""
+    import torch
+    p = ics.workload("plummer16k_adjoint")
+    eps, dt, steps = 1e-3, 1.0 / 128, 64
+    w = ics.rng(ics.seed_for(3), 9).normal(size=(3, p.n))
+    rx, rv, rm = oracle.hermite_shared_adjoint(p.pos, p.vel, p.mass, eps, dt, steps, w)
+    X, V, M, W = dev(p.pos), dev(p.vel), dev(p.mass), dev(w)
+    for prec, bar in (("ds", 1e-4), ("fp32", 1e-3)):
+        _, _, ck = ctx.shared_run(X, V, M, eps, dt, steps, prec=prec, ckpt_every=8)
+        gx, gv, gm = ctx.shared_adjoint(X, V, M, eps, dt, steps, ck, W, prec=prec, ckpt_every=8)
+        torch.cuda.synchronize()
+        st = {"gx0": rel_err_stats(host(gx), rx), "gv0": rel_err_stats(host(gv), rv),
+              "gm": scaled_err_stats(host(gm), rm)}
+        print(prec, "N=16384", {k: f"p99={v['p99']:.2e} max={v['max']:.2e}" for k, v in st.items()}, flush=True)
+        for k in st:
+            assert st[k]["p99"] <= bar, (prec, k, st[k])
