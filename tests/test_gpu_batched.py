@@ -141,3 +141,30 @@ def test_batch_hermite_graph_equals_eager_and_oracle(ctx):
         lo, hi = int(off[c]), int(off[c + 1])
         xr, _ = oracle.hermite_shared_forward(pos[:, lo:hi], vel[:, lo:hi], m[lo:hi], float(eps[c]), dt, steps)
         assert np.abs(xg[:, lo:hi] - xr).max() < 1e-7
+
+
+def test_clusters512_graph_run_against_oracle(ctx):
+    """The full batched workload: 512 clusters (N_c log-uniform in
+    [64, 8192], eps_c = 1/(4 N_c^(1/3))) advanced 32 shared Hermite steps of
+    1/256 through one captured hipGraph; 12 seeded clusters (including the
+    largest and the smallest) against the oracle's shared-step run."""
+    import torch
+    off, eps, p = ics.clusters(512, ics.seed_for(4))
+    sizes = np.diff(off)
+    X, V, M, O, E = dev(p.pos), dev(p.vel), dev(p.mass), dev(off), dev(eps)
+    a, j, _ = ctx.force_batched(X, V, M, O, E)
+    x, v = X.clone(), V.clone()
+    ctx.batch_hermite(x, v, a, j, M, O, E, 1.0 / 256, 32, use_graph=True)
+    torch.cuda.synchronize()
+    xg, vg = host(x), host(v)
+    g = np.random.default_rng(6)
+    picks = set(g.choice(512, 10, replace=False).tolist()) | {int(np.argmax(sizes)), int(np.argmin(sizes))}
+    worst = 0.0
+    for c in sorted(picks):
+        lo, hi = int(off[c]), int(off[c + 1])
+        xr, vr = oracle.hermite_shared_forward(p.pos[:, lo:hi], p.vel[:, lo:hi], p.mass[lo:hi], float(eps[c]),
+                                               1.0 / 256, 32)
+        dx = np.abs(xg[:, lo:hi] - xr).max()
+        worst = max(worst, dx)
+        assert dx < 1e-7 and np.abs(vg[:, lo:hi] - vr).max() < 1e-6, (c, hi - lo, dx)
+    print("512 clusters, 32 graph steps: worst max|dx| over", len(picks), "clusters", worst, flush=True)
