@@ -450,28 +450,27 @@ __global__ __launch_bounds__(256) void blk_reduce_correct_kernel(ReduceArgs r, C
     const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
     for (int64_t w = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; w < n; w += nw) {
         const int c = (int)w;
-        // the six quantities' loads of two ranges are in flight together; each
+        // the six quantities' loads of four ranges are in flight together; each
         // quantity still sums its ranges s = lane, lane + 64, ... in order
         double f[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
         const float2* col = r.part + c;
         const size_t qs = (size_t)n, rs = 7 * (size_t)n;
         int sp = lane;
-        for (; sp + 64 < S; sp += 128) {
-            float2 u[6], v[6];
+        for (; sp + 192 < S; sp += 256) {
+            float2 u[4][6];
 #pragma unroll
-            for (int q = 0; q < 6; ++q) {
-                u[q] = col[(size_t)sp * rs + q * qs];
-                v[q] = col[(size_t)(sp + 64) * rs + q * qs];
-            }
+            for (int h = 0; h < 4; ++h)
 #pragma unroll
-            for (int q = 0; q < 6; ++q) {
-                f[q] += (double)u[q].x;
-                f[q] += (double)u[q].y;
-                f[q] += (double)v[q].x;
-                f[q] += (double)v[q].y;
-            }
+                for (int q = 0; q < 6; ++q) u[h][q] = col[(size_t)(sp + 64 * h) * rs + q * qs];
+#pragma unroll
+            for (int h = 0; h < 4; ++h)
+#pragma unroll
+                for (int q = 0; q < 6; ++q) {
+                    f[q] += (double)u[h][q].x;
+                    f[q] += (double)u[h][q].y;
+                }
         }
-        if (sp < S) {
+        for (; sp < S; sp += 64) {
             float2 u[6];
 #pragma unroll
             for (int q = 0; q < 6; ++q) u[q] = col[(size_t)sp * rs + q * qs];
