@@ -92,9 +92,10 @@ def cpu_baseline(p, eps, budget_s):
     import oracle
     n = p.n
     t0 = time.perf_counter()
-    oracle.force(p.pos[:, :16], p.vel[:, :16], p.pos, p.vel, p.mass, eps, iself=np.arange(16))
-    t16 = time.perf_counter() - t0
-    k = int(max(16, min(4096, budget_s / max(t16, 1e-6) * 16)))
+    oracle.force(p.pos[:, :256], p.vel[:, :256], p.pos, p.vel, p.mass, eps, iself=np.arange(256))
+    t256 = time.perf_counter() - t0
+    # rows sized to fill about budget_s of host work (at least the 4096-row subset)
+    k = int(max(4096, min(n, budget_s / max(t256, 1e-6) * 256)))
     sel = np.arange(k)
     t0 = time.perf_counter()
     oracle.force(p.pos[:, sel], p.vel[:, sel], p.pos, p.vel, p.mass, eps, iself=sel)
