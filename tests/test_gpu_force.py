@@ -282,3 +282,37 @@ def test_autotune_cache_timing_and_reserve(tmp_path):
         assert (got["tile_j"], got["ipt"], got["wg"]) == (tile["tile_j"], tile["ipt"], tile["wg"])
     finally:
         c2.close()
+
+
+def test_work_on_a_caller_stream(ctx):
+    """Every call enqueues on the stream it is given: a force evaluation, a
+    block-step advance and the fused adjoint on a side stream (default
+    priority) give the same bits as on the current stream."""
+    import torch
+    p = ics.plummer(2500, 110, "salpeter")
+    X, V, M = dev(p.pos), dev(p.vel), dev(p.mass)
+    S = torch.arange(p.n, dtype=torch.int32, device="cuda")
+    ga = dev(np.random.default_rng(3).normal(size=(3, p.n)))
+    base = ctx.force(X, V, X, V, M, 1e-3, i_self=S)
+    gbase = ctx.force_vjp_self(X, V, M, 1e-3, ga)
+    h0 = ctx.hermite(p.n, eps=1e-3, eta=0.02, prec="ds")
+    h0.set_state(X, V, M)
+    h0.advance(1 << 12)
+    x0 = h0.get_state()["x"].clone()
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        Xs, Vs, Ms, Ss = X.clone(), V.clone(), M.clone(), S.clone()
+    got = ctx.force(Xs, Vs, Xs, Vs, Ms, 1e-3, i_self=Ss, stream=side)
+    ggot = ctx.force_vjp_self(Xs, Vs, Ms, 1e-3, ga, stream=side)
+    h1 = ctx.hermite(p.n, eps=1e-3, eta=0.02, prec="ds")
+    h1.set_state(Xs, Vs, Ms, stream=side)
+    h1.advance(1 << 12, stream=side)
+    x1 = h1.get_state(stream=side)["x"]
+    side.synchronize()
+    for u, w in zip(base, got):
+        assert torch.equal(u, w)
+    for u, w in zip(gbase, ggot):
+        assert torch.equal(u, w)
+    assert torch.equal(x0, x1)
+    h0.close(); h1.close()
