@@ -375,14 +375,17 @@ int nbody_hermite_get_state(nbody_hermite *h, hipStream_t stream, nbody_src P_ou
 
 /* One block step: select, predict all, evaluate the block, correct, new
  * steps.  *n_active and *t_ticks (HOST, may be NULL) receive the block size
- * and the new block time.  Synchronises `stream`. */
+ * and the new block time.  With block steps this synchronises `stream` (the
+ * block is chosen on the device and read back); with shared steps the block
+ * is every particle and nothing waits. */
 int nbody_hermite_step(nbody_hermite *h, hipStream_t stream, int64_t *n_active, int64_t *t_ticks);
 
 /* Block steps until the next block time would exceed t_end_ticks.  With
  * block steps the block size, the launch geometry of the pairwise kernel
- * (i-blocks, j-ranges) and the end-time gate are decided on the device by a
- * one-thread plan kernel; steps are enqueued in growing chunks (up to 64)
- * and the host reads the plan's statistics once per chunk.  A step whose
+ * (i-blocks, j-ranges) and the end-time gate are decided on the device, by
+ * one thread at the end of the selection pass; steps are enqueued in growing
+ * chunks (up to 64) and the host reads the plan's statistics once per chunk
+ * (so the call returns with `stream` synchronised).  A step whose
  * block time lies beyond t_end_ticks leaves the state untouched.  With
  * shared steps the block is always every particle and nothing is read
  * back. */
