@@ -264,18 +264,27 @@ def block_run(n, t_end, precs, report_every=0.0, ctx=None, marks_out=True):
         chunk = max(1, int(round((report_every or t_end) * (1 << 20))))
         target = 0
         marks = []
+        diag = 0.0   # wall time spent in energy diagnostics, not counted
         while target < T:
             target = min(T, target + chunk)
             st = h.advance(target)
             torch.cuda.synchronize()
-            el = time.perf_counter() - t0
-            marks.append({"t": st["t_ticks"] / (1 << 20), "steps": st["steps"], "sum_active": st["sum_active"],
-                          "wall_s": round(el, 3)})
+            el = time.perf_counter() - t0 - diag
+            mark = {"t": st["t_ticks"] / (1 << 20), "steps": st["steps"], "sum_active": st["sum_active"],
+                    "wall_s": round(el, 3)}
+            if report_every and target < T:
+                d0 = time.perf_counter()
+                ekm, epm = h.energy()
+                mark["dE_over_E"] = (ekm + epm - e0) / e0
+                diag += time.perf_counter() - d0
+            marks.append(mark)
             log(f"[block] {prec} t={st['t_ticks'] / (1 << 20):.5f} steps={st['steps']} "
                 f"sum_active={st['sum_active']} wall={el:.1f}s")
-        wall = time.perf_counter() - t0
+        wall = time.perf_counter() - t0 - diag
         ek, ep = h.energy()
         e1 = ek + ep
+        if marks:
+            marks[-1]["dE_over_E"] = (e1 - e0) / e0
         inter = float(st["sum_active"]) * n
         out["runs"][prec] = {
             "wall_s": round(wall, 3), "block_steps": st["steps"], "sum_active": st["sum_active"],
@@ -283,6 +292,7 @@ def block_run(n, t_end, precs, report_every=0.0, ctx=None, marks_out=True):
             "Gint_s": round(inter / wall / 1e9, 3), "t_end": st["t_ticks"] / (1 << 20),
             "E0": e0, "E1": e1, "dE_over_E": (e1 - e0) / e0,
             "drift_per_time_unit": abs((e1 - e0) / e0) / max(st["t_ticks"] / (1 << 20), 1e-30),
+            "max_abs_dE_over_E": max([abs(mk["dE_over_E"]) for mk in marks if "dE_over_E" in mk] + [abs((e1 - e0) / e0)]),
             "us_per_block_step": round(wall / max(st["steps"], 1) * 1e6, 2),
         }
         if marks_out:
