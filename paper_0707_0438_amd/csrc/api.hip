@@ -679,9 +679,11 @@ int nbody_hermite_create(nbody_ctx* c, nbody_hermite** hp, int64_t n, const nbod
     h->n = n;
     h->o = *o;
     const size_t nn = (size_t)n;
-    const size_t bytes = sizeof(double) * nn * (13 + 1 + 7 + 6) + sizeof(int64_t) * nn * 2 +
-                         sizeof(int32_t) * nn + sizeof(int64_t) * 8 + sizeof(double) * 2 + sizeof(DevPlan) +
-                         8192;
+    // every piece below starts on a 256-byte boundary
+    auto r256 = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    const size_t bytes = (13 + 7 + 6) * r256(sizeof(double) * nn) + 2 * r256(sizeof(int64_t) * nn) +
+                         r256(sizeof(int32_t) * nn) + r256(sizeof(int64_t) * 2) + r256(sizeof(int64_t)) +
+                         r256(sizeof(double) * 2) + r256(sizeof(DevPlan));
     ++c->alloc_count;
     if (c->fail_alloc_at > 0 && c->alloc_count == c->fail_alloc_at) {
         delete h;
