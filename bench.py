@@ -235,6 +235,40 @@ def kinds_timing(ctx, X, V, M, eps, prec, full_kernel_ms, reps=2):
     return out
 
 
+def shared1k_timing(ctx, reps=5):
+    """The N = 1024 shared-step workload (equal-mass Plummer, eps = 1/256,
+    dt = 1/256 to t = 1/8, 32 steps): wall time per step (best of reps, state
+    reset each time) in both precisions, and the largest position difference
+    from the float64 oracle's run at the end."""
+    import numpy as np
+    import torch
+    import nbody_inputs as ics
+    import oracle
+    p = ics.workload("plummer1k_hermite")
+    X, V, M = (torch.from_numpy(a).to("cuda") for a in (p.pos, p.vel, p.mass))
+    ref = oracle.HermiteState(p.pos, p.vel, p.mass)
+    t0 = time.perf_counter()
+    oracle.hermite_run(ref, (1 << 20) // 8, eps=1.0 / 256, shared_log2=-8, init=True)
+    t_oracle = time.perf_counter() - t0
+    out = {"workload": "plummer1k_hermite: N=1024 equal-mass Plummer, eps=1/256, 32 shared Hermite steps of 1/256",
+           "oracle_s": round(t_oracle, 4), "oracle_cores": oracle.num_threads()}
+    for prec in ("ds", "fp32"):
+        h = ctx.hermite(p.n, eps=1.0 / 256, shared_dt_log2=-8, prec=prec)
+        best = 1e30
+        for _ in range(reps):
+            h.set_state(X, V, M)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st = h.advance((1 << 20) // 8)
+            torch.cuda.synchronize()
+            best = min(best, time.perf_counter() - t0)
+        x = h.get_state()["x"].cpu().numpy()
+        out[prec] = {"us_per_step": round(best / st["steps"] * 1e6, 2), "steps": st["steps"],
+                     "max_abs_dx_vs_oracle": float(np.abs(x - ref.x).max())}
+        h.close()
+    return out
+
+
 def block_run(n, t_end, precs, report_every=0.0, ctx=None, marks_out=True):
     """Hermite block steps on the Salpeter workload (Plummer positions and
     velocities, Salpeter masses 0.1-100 normalised to 1, eps = 1e-3,
@@ -335,8 +369,8 @@ def main():
     ap.add_argument("--block-run", action="store_true",
                     help="only run the Salpeter block-step workload (--n, --t-end) and print its JSON")
     ap.add_argument("--t-end", type=float, default=1.0)
-    ap.add_argument("--extras", default="batched,adjoint,kinds,block",
-                    help="comma list of extra measurements (batched, adjoint, kinds, block) or 'none'")
+    ap.add_argument("--extras", default="batched,adjoint,kinds,block,shared1k",
+                    help="comma list of extra measurements (batched, adjoint, kinds, block, shared1k) or 'none'")
     ap.add_argument("--report-every", type=float, default=0.0)
     args = ap.parse_args()
     if args.copy_calibration:
@@ -445,6 +479,9 @@ def main():
     if "block" in extras:
         log("[bench] block steps, Salpeter N=65536 to t=1/4")
         line["block_steps"] = block_run(65536, 0.25, ["ds", "fp32"], ctx=ctx, marks_out=False)
+    if "shared1k" in extras:
+        log("[bench] shared steps, N=1024")
+        line["shared1k"] = shared1k_timing(ctx)
     if args.cpu_budget > 0:
         log("[bench] cpu baseline (oracle)")
         line["cpu_baseline"] = cpu_baseline(p, eps, args.cpu_budget)
