@@ -12,6 +12,7 @@ Prints ONE JSON line (rank 0, N = 1):
   roofline  the pairwise kernel against the FP32 vector peak, from HIP events
             recorded around each kernel launch on its stream
   cpu_baseline  the float64 oracle on a bounded i-subset on the host's cores
+  accuracy  per-particle relative errors of both precisions on that subset
 """
 from __future__ import annotations
 
@@ -57,15 +58,36 @@ def traffic_per_launch(prec: str):
         return None
 
 
+def device_clock_ghz():
+    """Peak engine clock the HIP runtime reports for device 0 (GHz), or None."""
+    import ctypes
+    import paper_0707_0438_amd as nb
+    try:
+        hip = ctypes.CDLL(nb.LIB_PATH)   # resolves the runtime libnbody links
+        khz = ctypes.c_int(0)
+        # hipDeviceAttributeClockRate (5): peak clock in kHz
+        if hip.hipDeviceGetAttribute(ctypes.byref(khz), 5, 0) != 0 or khz.value <= 0:
+            return None
+        return khz.value / 1e6
+    except (OSError, AttributeError):
+        return None
+
+
 def device_info():
     """What the runtime reports about the GPU, and how the FP32 peak used for
-    the roofline is derived."""
+    the roofline is derived (the published 157.3 TFLOP/s is the one used)."""
     import torch
     pr = torch.cuda.get_device_properties(0)
-    return {"name": pr.name, "arch": getattr(pr, "gcnArchName", ""), "compute_units": pr.multi_processor_count,
+    cu = pr.multi_processor_count
+    ghz = device_clock_ghz()
+    info = {"name": pr.name, "arch": getattr(pr, "gcnArchName", ""), "compute_units": cu,
             "memory_GiB": round(pr.total_memory / 2 ** 30, 1),
-            "fp32_peak": f"{pr.multi_processor_count} CU x 64 lanes x 2 (packed FP32 rate) x 2 (FMA) x 2.4 GHz "
-                         f"= {pr.multi_processor_count * 64 * 2 * 2 * 2.4e9 / 1e12:.1f} TFLOP/s"}
+            "fp32_peak": f"{cu} CU x 64 lanes x 2 (packed FP32 rate) x 2 (FMA) x 2.4 GHz "
+                         f"= {cu * 64 * 2 * 2 * 2.4e9 / 1e12:.1f} TFLOP/s"}
+    if ghz:
+        info["reported_peak_clock_GHz"] = round(ghz, 3)
+        info["fp32_peak_at_reported_clock_TFLOP_s"] = round(cu * 64 * 2 * 2 * ghz * 1e9 / 1e12, 1)
+    return info
 
 
 def time_steps(ctx, h, steps, warmup):
@@ -88,6 +110,9 @@ def time_steps(ctx, h, steps, warmup):
 
 
 def cpu_baseline(p, eps, budget_s):
+    """Time the float64 oracle on the first k particles against all n.
+    Returns the baseline record and the oracle's rows (for the accuracy
+    report)."""
     import numpy as np
     import oracle
     n = p.n
@@ -98,12 +123,42 @@ def cpu_baseline(p, eps, budget_s):
     k = int(max(4096, min(n, budget_s / max(t256, 1e-6) * 256)))
     sel = np.arange(k)
     t0 = time.perf_counter()
-    oracle.force(p.pos[:, sel], p.vel[:, sel], p.pos, p.vel, p.mass, eps, iself=sel)
+    ref = oracle.force(p.pos[:, sel], p.vel[:, sel], p.pos, p.vel, p.mass, eps, iself=sel)
     dt = time.perf_counter() - t0
     return {"value": round(k * n / dt / 1e9, 6), "unit": "Ginteractions/s",
             "cores": oracle.num_threads(), "kind": "oracle",
             "sample": f"float64 oracle force (acc+jerk+pot) of the first {k} particles against "
-                      f"all {n} (eps={eps}), {dt:.1f} s"}
+                      f"all {n} (eps={eps}), {dt:.1f} s"}, ref, k
+
+
+def rel_error_stats(got, ref):
+    """Per-particle relative errors |g - r| / |r| of acceleration, jerk (3-vectors,
+    rows [3, k]) and potential: p99 (nearest rank) and maximum."""
+    import numpy as np
+
+    def stats(e):
+        e = np.sort(e)
+        return {"p99": float(f"{e[int(np.ceil(0.99 * e.size)) - 1]:.3e}"), "max": float(f"{e[-1]:.3e}")}
+
+    out = {}
+    for name, g, r in zip(("acc", "jerk"), got[:2], ref[:2]):
+        out[name] = stats(np.linalg.norm(g - r, axis=0) / np.linalg.norm(r, axis=0))
+    out["pot"] = stats(np.abs(got[2] - ref[2]) / np.abs(ref[2]))
+    return out
+
+
+def accuracy(ctx, X, V, M, eps, ref, k):
+    """Both precisions of the N = n evaluation on the oracle's k rows."""
+    import torch
+    S = torch.arange(X.shape[1], dtype=torch.int32, device="cuda")
+    out = {"sample": f"the first {k} particles against the float64 oracle (the cpu_baseline rows); "
+                     "per-particle |d|/|ref|, p99 by nearest rank"}
+    for prec in ("ds", "fp32"):
+        a, j, pt = ctx.force(X, V, X, V, M, eps, prec=prec, i_self=S)
+        torch.cuda.synchronize()
+        got = (a[:, :k].cpu().numpy(), j[:, :k].cpu().numpy(), pt[:k].cpu().numpy())
+        out["ds_comp" if prec == "ds" else "fp32"] = rel_error_stats(got, ref)
+    return out
 
 
 def adjoint_timing(nb, ctx, prec, reps=10):
@@ -484,7 +539,9 @@ def main():
         line["shared1k"] = shared1k_timing(ctx)
     if args.cpu_budget > 0:
         log("[bench] cpu baseline (oracle)")
-        line["cpu_baseline"] = cpu_baseline(p, eps, args.cpu_budget)
+        line["cpu_baseline"], ref, k = cpu_baseline(p, eps, args.cpu_budget)
+        log("[bench] accuracy of both precisions on the oracle's rows")
+        line["accuracy"] = accuracy(ctx, X, V, M, eps, ref, k)
     ctx.close()
     print(json.dumps(line), flush=True)
 
