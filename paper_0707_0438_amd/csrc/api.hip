@@ -67,6 +67,8 @@ struct nbody_hermite {
     int64_t* tnow = nullptr;  // device scalar: latest block time
     double* e2 = nullptr;     // device [2]
     DevPlan* plan = nullptr;  // device block-step plan and statistics
+    float4* spack = nullptr;  // shared steps: records of all particles predicted to spack_tn
+    int64_t spack_tn = -1;    // tick those records are valid for (-1: none)
     int64_t t_ticks = 0;
     int64_t steps = 0, sum_active = 0;
     void* block = nullptr;    // single allocation holding everything above
@@ -210,7 +212,8 @@ static nbody_tile pick_tile(nbody_ctx* c, int prec, int64_t ni, int64_t nj) {
 static int run_force(nbody_ctx* c, hipStream_t st, int prec, double G, double eps, int64_t ni,
                      const float4* ipack, const int32_t* iidx, const int32_t* iself, int self_mode,
                      int64_t nj, const float4* jpack, double* const out[7], const nbody_tile* forced,
-                     int kind = 0, int32_t* nn = nullptr, double* nn_r2 = nullptr) {
+                     int kind = 0, int32_t* nn = nullptr, double* nn_r2 = nullptr,
+                     int* defer_split = nullptr) {
     if (ni == 0) return NBODY_OK;
     nbody_tile t;
     if (forced) {
@@ -283,6 +286,11 @@ static int run_force(nbody_ctx* c, hipStream_t st, int prec, double G, double ep
     hipError_t e = launch_force(prec, ipt, tj, wg, jsrc, unr, wpe, eps0, nb, S, a, st, kind);
     if (e != hipSuccess) return hip_err(c, e, "force kernel launch");
     if (te && hipEventRecord(te, st) != hipSuccess) return set_err(c, NBODY_ERR_DEVICE, "event record");
+    if (defer_split) {
+        // the caller reduces the partials (kind 0 only) in a kernel of its own
+        *defer_split = S;
+        return NBODY_OK;
+    }
     if (S > 1) {
         ReduceArgs r{};
         r.ni = (int)ni;
@@ -683,7 +691,8 @@ int nbody_hermite_create(nbody_ctx* c, nbody_hermite** hp, int64_t n, const nbod
     auto r256 = [](size_t b) { return (b + 255) & ~(size_t)255; };
     const size_t bytes = (13 + 7 + 6) * r256(sizeof(double) * nn) + 2 * r256(sizeof(int64_t) * nn) +
                          r256(sizeof(int32_t) * nn) + r256(sizeof(int64_t) * 2) + r256(sizeof(int64_t)) +
-                         r256(sizeof(double) * 2) + r256(sizeof(DevPlan));
+                         r256(sizeof(double) * 2) + r256(sizeof(DevPlan)) +
+                         r256(sizeof(float4) * kRecDS * nn);
     ++c->alloc_count;
     if (c->fail_alloc_at > 0 && c->alloc_count == c->fail_alloc_at) {
         delete h;
@@ -711,6 +720,7 @@ int nbody_hermite_create(nbody_ctx* c, nbody_hermite** hp, int64_t n, const nbod
     h->tnow = (int64_t*)take(sizeof(int64_t));
     h->e2 = (double*)take(sizeof(double) * 2);
     h->plan = (DevPlan*)take(sizeof(DevPlan));
+    h->spack = (float4*)take(sizeof(float4) * kRecDS * nn);
     *hp = h;
     return NBODY_OK;
 }
@@ -769,6 +779,7 @@ int nbody_hermite_set_state(nbody_hermite* h, hipStream_t st, nbody_src P) {
     e = launch_init_dt(a, st);
     if (e != hipSuccess) return hip_err(c, e, "init dt launch");
     h->has_state = true;
+    h->spack_tn = -1;
     h->t_ticks = 0;
     h->steps = 0;
     h->sum_active = 0;
@@ -801,12 +812,17 @@ static int plan_read(nbody_hermite* h, hipStream_t st, DevPlan* p) {
     return NBODY_OK;
 }
 
-static int pack_predicted(nbody_hermite* h, hipStream_t st, int64_t tn) {
+// Predict every particle to tick tn and pack it, into `out` (NULL: the
+// context's j-pack buffer).
+static int pack_predicted(nbody_hermite* h, hipStream_t st, int64_t tn, float4* out = nullptr) {
     nbody_ctx* c = h->ctx;
     const int p = (int)h->o.prec;
     const int n = (int)h->n;
-    int rc = dev_alloc(c, c->jpack, sizeof(float4) * rec_words(p) * (size_t)n);
-    if (rc) return rc;
+    if (!out) {
+        int rc = dev_alloc(c, c->jpack, sizeof(float4) * rec_words(p) * (size_t)n);
+        if (rc) return rc;
+        out = (float4*)c->jpack.p;
+    }
     PackArgs pa{};
     pa.n = n;
     pa.prec = p;
@@ -818,7 +834,7 @@ static int pack_predicted(nbody_hermite* h, hipStream_t st, int64_t tn) {
     pa.t = h->t;
     pa.tnext = nullptr;
     pa.tn = tn;
-    pa.out = (float4*)c->jpack.p;
+    pa.out = out;
     hipError_t e = launch_pack(pa, st);
     if (e != hipSuccess) return hip_err(c, e, "predict/pack launch");
     return NBODY_OK;
@@ -846,25 +862,50 @@ static CorrectArgs correct_args(nbody_hermite* h, int n_act) {
 
 // Shared steps: every particle is due every step, so the block (all n, in
 // order) and its time are known on the host: no selection pass, the block
-// time goes to the kernels by value, and the i-list is the identity.
+// time goes to the kernels by value, and the i-list is the identity.  Two
+// kernels per step: the pairwise kernel, then split reduce + corrector +
+// prediction and packing of every particle for the next step (its records
+// live in h->spack; a pack pass runs only when they are not current).
 static int hermite_step_shared(nbody_hermite* h, hipStream_t st, int64_t t_limit, bool* stopped) {
     nbody_ctx* c = h->ctx;
     const int n = (int)h->n;
-    const int64_t tn = h->t_ticks + ((int64_t)1 << (h->o.shared_dt_log2 + 20));
+    const int64_t dtk = (int64_t)1 << (h->o.shared_dt_log2 + 20);
+    const int64_t tn = h->t_ticks + dtk;
     *stopped = tn > t_limit;
     if (*stopped) return NBODY_OK;
-    int rc = pack_predicted(h, st, tn);
-    if (rc) return rc;
+    if (h->spack_tn != tn) {
+        int rc = pack_predicted(h, st, tn, h->spack);
+        if (rc) return rc;
+        h->spack_tn = tn;
+    }
     const int p = (int)h->o.prec;
-    rc = run_force(c, st, p, h->o.G, h->o.eps, n, (const float4*)c->jpack.p, nullptr, nullptr, 2, n,
-                   (const float4*)c->jpack.p, h->f, nullptr);
+    int S = 1;
+    int rc = run_force(c, st, p, h->o.G, h->o.eps, n, h->spack, nullptr, nullptr, 2, n, h->spack, h->f, nullptr,
+                       0, nullptr, nullptr, &S);
     if (rc) return rc;
+    ReduceArgs r{};
+    r.ni = n;
+    r.nj = n;
+    r.S = S;
+    r.prec = p;
+    r.part = (const float2*)c->part.p;
+    r.G = h->o.G;
+    r.plan = nullptr;
     CorrectArgs ca = correct_args(h, n);
     ca.idx = nullptr;
     ca.tnext = nullptr;
     ca.tn = tn;
-    hipError_t e = launch_correct(ca, st);
-    if (e != hipSuccess) return hip_err(c, e, "corrector launch");
+    ca.m = h->s[12];
+    ca.pack_next = h->spack;
+    ca.tn_next = tn + dtk;
+    ca.pack_prec = p;
+    // a wave per particle for the split reduce, else a thread per particle
+    const int64_t threads = S > 1 ? 64 * (int64_t)n : (int64_t)n;
+    const int grid = (int)std::min<int64_t>(1024, (threads + 255) / 256);
+    h->spack_tn = -1;   // the records are being rewritten
+    hipError_t e = launch_blk_reduce_correct(r, ca, grid, st);
+    if (e != hipSuccess) return hip_err(c, e, "reduce/corrector launch");
+    h->spack_tn = tn + dtk;
     h->t_ticks = tn;
     h->steps += 1;
     h->sum_active += n;
@@ -1118,6 +1159,7 @@ int nbody_hermite_load(nbody_hermite* h, hipStream_t st, const void* buf) {
     h->steps = hdr[2];
     h->sum_active = hdr[3];
     h->has_state = true;
+    h->spack_tn = -1;
     return NBODY_OK;
 }
 

@@ -405,6 +405,22 @@ __device__ __forceinline__ void correct_core(const CorrectArgs& a, int c, const 
         J[k][i] = j1[k];
     }
     a.t[i] = tn;
+    if (a.pack_next) {
+        // the next shared step's record of this particle, from the state just
+        // written (read back through memory, as a pack pass reads it)
+        PackArgs p{};
+        p.x = a.x; p.y = a.y; p.z = a.z;
+        p.vx = a.vx; p.vy = a.vy; p.vz = a.vz;
+        p.m = a.m;
+        p.ax = a.ax; p.ay = a.ay; p.az = a.az;
+        p.jx = a.jx; p.jy = a.jy; p.jz = a.jz;
+        p.t = a.t;
+        p.out = a.pack_next;
+        if (a.pack_prec == 1)
+            pack_one<1>(p, i, a.tn_next);
+        else
+            pack_one<0>(p, i, a.tn_next);
+    }
     if (!a.shared) {
         const double b0 = a2[0] + a3[0] * D, b1 = a2[1] + a3[1] * D, b2 = a2[2] + a3[2] * D;
         const double na = norm3(a1[0], a1[1], a1[2]), nj = norm3(j1[0], j1[1], j1[2]);
@@ -437,10 +453,11 @@ __global__ __launch_bounds__(256) void init_dt_kernel(InitDtArgs a) {
 // lane-strided sums and butterfly as the wave-per-row split reduce, so the same
 // bits) fused with the corrector, one wave per active particle.  Without a
 // split the pairwise kernel has written the forces and only the corrector
-// runs.
+// runs.  Shared steps use it without a device plan, with the next step's
+// prediction and packing fused in as well (CorrectArgs.pack_next).
 __global__ __launch_bounds__(256) void blk_reduce_correct_kernel(ReduceArgs r, CorrectArgs ca) {
     const DevPlan* pl = r.plan;
-    const int n = (int)pl->n_act, S = pl->S;
+    const int n = pl ? (int)pl->n_act : r.ni, S = pl ? pl->S : r.S;
     if (n <= 0) return;
     if (S <= 1) {
         for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x) correct_one(ca, c);

@@ -24,9 +24,12 @@ inline int rec_words(int prec) { return prec == 0 ? kRecFP32 : kRecDS; }
 // nb i-blocks of per_blk particles and S j-ranges of jchunk records (a
 // multiple of the tile).  Enough work-groups to cover the 256 CUs several
 // times, with at least min_tiles tiles per j-range.  Used by the host for direct
-// calls and by the device for block steps whose size only it knows.
+// calls and by the device for block steps whose size only it knows.  Small
+// self-gravitating sets are latency-bound: a j-range of one tile per
+// work-group was the fastest on MI355X from N = 256 to 4096 (N = 1024:
+// pairwise 10.7 us against 28 us with four tiles per range).
 __host__ __device__ inline void split_plan(int64_t ni, int64_t nj, int per_blk, int tile_j, int split_req,
-                                           int* nb_out, int* S_out, int* jchunk_out, int min_tiles = 4) {
+                                           int* nb_out, int* S_out, int* jchunk_out, int min_tiles = 1) {
     const int64_t nb = (ni + per_blk - 1) / per_blk;
     int64_t S = split_req;
     if (S <= 0) {
@@ -177,6 +180,13 @@ struct CorrectArgs {
     double eta;
     int lmin, lmax, shared;           // shared != 0: keep dt
     int64_t* tnow;                    // receives the block time (written by one thread; may be NULL)
+    // Shared steps: after its correction each particle is predicted to
+    // tick tn_next and its record written to pack_next in precision
+    // pack_prec (pack_one, so the same bits as a pack pass).  NULL: not done.
+    const double* m;
+    float4* pack_next;
+    int64_t tn_next;
+    int pack_prec;
 };
 hipError_t launch_correct(const CorrectArgs& a, hipStream_t st);
 
@@ -187,6 +197,7 @@ int blk_scratch_words(int n);
 hipError_t launch_blk_front(const PackArgs& pa, const int64_t* dt, int32_t* idx, int64_t* sel2, DevPlan* plan,
                             int64_t* scratch, int per_blk, int tile_j, hipStream_t st);
 // Block steps: split reduce (when the plan has S > 1) fused with the corrector.
+// With r.plan NULL the block is particles 0 .. r.ni-1 and the split is r.S.
 hipError_t launch_blk_reduce_correct(const ReduceArgs& r, const CorrectArgs& ca, int grid, hipStream_t st);
 
 // First steps after the initial force evaluation.
