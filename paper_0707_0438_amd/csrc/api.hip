@@ -215,6 +215,7 @@ static int run_force(nbody_ctx* c, hipStream_t st, int prec, double G, double ep
                      int kind = 0, int32_t* nn = nullptr, double* nn_r2 = nullptr,
                      int* defer_split = nullptr) {
     if (ni == 0) return NBODY_OK;
+    if (defer_split && kind != 0) return set_err(c, NBODY_ERR_ARG, "deferred split reduce needs kind 0");
     nbody_tile t;
     if (forced) {
         t = *forced;

@@ -119,6 +119,66 @@ def test_block_steps_salpeter_reduced(ctx, prec):
     assert drift_gpu < max(1e-5, 10 * drift_ref)
 
 
+@pytest.mark.parametrize("prec", ["ds", "fp32"])
+def test_shared_steps_survive_interleaved_calls(ctx, prec):
+    """Shared steps keep the next step's records from the fused corrector.
+    Energy evaluations, direct force calls on the same context, state reads,
+    a save/load into a new driver and a fresh set_state between steps must
+    not change a bit of the trajectory (N = 700, a ragged size)."""
+    p = ics.plummer(700, 204)
+    eps, T = 1.0 / 128, TICKS // 16     # 16 steps of 2^-8
+    X, V, M = dev(p.pos), dev(p.vel), dev(p.mass)
+    h = ctx.hermite(p.n, eps=eps, shared_dt_log2=-8, prec=prec)
+    h.set_state(X, V, M)
+    h.advance(T)
+    ref = gpu_state(h)
+    # the same run with other work between the steps
+    h.set_state(X, V, M)                # records of the old run are stale now
+    S = dev(np.arange(p.n, dtype=np.int32))
+    for _ in range(8):
+        h.step()
+        h.energy()
+        ctx.force(X, V, X, V, M, eps, prec=prec, i_self=S)
+        gpu_state(h)
+    blob = h.save()
+    h2 = ctx.hermite(p.n, eps=eps, shared_dt_log2=-8, prec=prec)
+    h2.load(blob)
+    for _ in range(8):
+        h2.step()
+        ctx.force(X, V, X, V, M, eps, prec=prec, i_self=S)
+    got = gpu_state(h2)
+    for k in ref:
+        assert np.array_equal(got[k], ref[k]), k
+
+
+@pytest.mark.parametrize("prec", ["ds", "fp32"])
+def test_shared_steps_without_split(ctx, prec):
+    """The same kind of run with the pairwise kernel forced to one j-range
+    (the corrector then reads the forces directly, no split reduce) against
+    the oracle."""
+    p = ics.plummer(600, 205)
+    eps, T = 1.0 / 128, TICKS // 16
+    ref = oracle.HermiteState(p.pos, p.vel, p.mass)
+    oracle.hermite_run(ref, T, eps=eps, shared_log2=-8, init=True)
+    ctx.set_tile(prec, tile_j=64, ipt=1, wg=128, split=1)
+    try:
+        assert ctx.get_tile(p.n, p.n, prec)["split"] == 1
+        h = ctx.hermite(p.n, eps=eps, shared_dt_log2=-8, prec=prec)
+        h.set_state(dev(p.pos), dev(p.vel), dev(p.mass))
+        st = h.advance(T)
+        s = gpu_state(h)
+    finally:
+        ctx.set_tile(prec)
+    assert st["steps"] == 16
+    dx = np.abs(s["x"] - ref.x).max()
+    dv = np.abs(s["v"] - ref.v).max()
+    print(prec, "split 1: max|dx|", dx, "max|dv|", dv, flush=True)
+    if prec == "ds":
+        assert dx <= 1e-8 and dv <= 1e-7
+    else:
+        assert dx <= 1e-6 and dv <= 1e-5
+
+
 def test_save_load_continues_bit_identically(ctx):
     p = ics.plummer(1500, 201, "salpeter")
     h = ctx.hermite(p.n, eps=1e-3, eta=0.02, prec="ds")
