@@ -69,6 +69,9 @@ struct nbody_hermite {
     DevPlan* plan = nullptr;  // device block-step plan and statistics
     float4* spack = nullptr;  // shared steps: records of all particles predicted to spack_tn
     int64_t spack_tn = -1;    // tick those records are valid for (-1: none)
+    int64_t* gmin2 = nullptr; // block steps: two arrays of chunk minima of t + dt (this step's, next)
+    int gpar = 0;             // which of the two holds this step's
+    bool gmin_ok = false;     // false: recompute this step's before use
     int64_t t_ticks = 0;
     int64_t steps = 0, sum_active = 0;
     void* block = nullptr;    // single allocation holding everything above
@@ -693,7 +696,7 @@ int nbody_hermite_create(nbody_ctx* c, nbody_hermite** hp, int64_t n, const nbod
     const size_t bytes = (13 + 7 + 6) * r256(sizeof(double) * nn) + 2 * r256(sizeof(int64_t) * nn) +
                          r256(sizeof(int32_t) * nn) + r256(sizeof(int64_t) * 2) + r256(sizeof(int64_t)) +
                          r256(sizeof(double) * 2) + r256(sizeof(DevPlan)) +
-                         r256(sizeof(float4) * kRecDS * nn);
+                         r256(sizeof(float4) * kRecDS * nn) + r256(sizeof(int64_t) * blk_scratch_words((int)n));
     ++c->alloc_count;
     if (c->fail_alloc_at > 0 && c->alloc_count == c->fail_alloc_at) {
         delete h;
@@ -722,6 +725,7 @@ int nbody_hermite_create(nbody_ctx* c, nbody_hermite** hp, int64_t n, const nbod
     h->e2 = (double*)take(sizeof(double) * 2);
     h->plan = (DevPlan*)take(sizeof(DevPlan));
     h->spack = (float4*)take(sizeof(float4) * kRecDS * nn);
+    h->gmin2 = (int64_t*)take(sizeof(int64_t) * blk_scratch_words((int)n));
     *hp = h;
     return NBODY_OK;
 }
@@ -781,6 +785,7 @@ int nbody_hermite_set_state(nbody_hermite* h, hipStream_t st, nbody_src P) {
     if (e != hipSuccess) return hip_err(c, e, "init dt launch");
     h->has_state = true;
     h->spack_tn = -1;
+    h->gmin_ok = false;
     h->t_ticks = 0;
     h->steps = 0;
     h->sum_active = 0;
@@ -931,8 +936,13 @@ static int hermite_enqueue_block(nbody_hermite* h, hipStream_t st) {
     pa.jx = h->s[9]; pa.jy = h->s[10]; pa.jz = h->s[11];
     pa.t = h->t;
     pa.out = (float4*)c->jpack.p;
-    hipError_t e = launch_blk_front(pa, h->dt, h->idx, h->sel2, h->plan, (int64_t*)c->sel.p + 2,
-                                    kBlkWG * kBlkIPT, kBlkTile, st);
+    const int G = blk_scratch_words(n) / 2;
+    int64_t* gmin = h->gmin2 + (size_t)h->gpar * G;
+    int64_t* gmin_next = h->gmin2 + (size_t)(h->gpar ^ 1) * G;
+    const bool need_min = !h->gmin_ok;
+    h->gmin_ok = false;   // until every launch of this step is in
+    hipError_t e = launch_blk_front(pa, h->dt, h->idx, h->sel2, h->plan, (int64_t*)c->sel.p + 2, gmin, gmin_next,
+                                    need_min, kBlkWG * kBlkIPT, kBlkTile, st);
     if (e != hipSuccess) return hip_err(c, e, "select/pack/plan launch");
     ForceArgs a{};
     a.ipack = (const float4*)c->jpack.p;
@@ -965,8 +975,13 @@ static int hermite_enqueue_block(nbody_hermite* h, hipStream_t st) {
     r.plan = h->plan;
     // 1024 work-groups: 4096 waves for the wave-per-particle split reduce,
     // 262144 threads for the corrector alone; both stride over larger blocks
-    e = launch_blk_reduce_correct(r, correct_args(h, n), 1024, st);
+    CorrectArgs ca = correct_args(h, n);
+    ca.gmin_next = gmin_next;
+    ca.gch = blk_chunk_size(n);
+    e = launch_blk_reduce_correct(r, ca, 1024, st);
     if (e != hipSuccess) return hip_err(c, e, "reduce/corrector launch");
+    h->gpar ^= 1;
+    h->gmin_ok = true;
     return NBODY_OK;
 }
 
@@ -1161,6 +1176,7 @@ int nbody_hermite_load(nbody_hermite* h, hipStream_t st, const void* buf) {
     h->sum_active = hdr[3];
     h->has_state = true;
     h->spack_tn = -1;
+    h->gmin_ok = false;
     return NBODY_OK;
 }
 

@@ -206,7 +206,8 @@ hipError_t launch_select(int n, const int64_t* t, const int64_t* dt, int32_t* id
 // The selection of a block step fused with the work that depends only on its
 // result, in three passes over chunks of `ch` entries (a power of two chosen
 // so that about kBlkGroups work-groups share the particles):
-//   1. chunk minima of t + dt;
+//   1. chunk minima of t + dt (only after the state was set or loaded:
+//      afterwards pass 2 and the corrector keep them, see below);
 //   2. the global minimum t_next, each chunk's count of particles due at
 //      t_next, and the prediction of every particle of the chunk to t_next
 //      packed into j records;
@@ -240,9 +241,14 @@ __global__ __launch_bounds__(kSelWG) void blk_min_kernel(int n, int ch, const in
     if (threadIdx.x == 0) gmin[blockIdx.x] = m;
 }
 
+// gmin holds this step's chunk minima.  gmin_next receives, per chunk, the
+// minimum of t + dt over the particles that are not due (the corrector then
+// lowers it with the new t + dt of the due ones), so the next step needs no
+// minimum pass; a step past the end time copies gmin unchanged.
 template <int PREC>
 __global__ __launch_bounds__(kSelWG) void blk_count_pack_kernel(int ch, int G, const int64_t* __restrict__ dt,
                                                                 const int64_t* __restrict__ gmin,
+                                                                int64_t* __restrict__ gmin_next,
                                                                 int64_t* __restrict__ gcnt,
                                                                 int64_t* __restrict__ sel2,
                                                                 const DevPlan* __restrict__ plan, PackArgs pa) {
@@ -252,14 +258,21 @@ __global__ __launch_bounds__(kSelWG) void blk_count_pack_kernel(int ch, int G, c
     const int64_t tn = block_min_i64(m, red);
     const int base = blockIdx.x * ch;
     const int end = min(pa.n, base + ch);
-    int64_t c = 0;
-    for (int k = base + threadIdx.x; k < end; k += kSelWG) c += (pa.t[k] + dt[k] == tn) ? 1 : 0;
+    int64_t c = 0, rest = INT64_MAX;
+    for (int k = base + threadIdx.x; k < end; k += kSelWG) {
+        const int64_t v = pa.t[k] + dt[k];
+        c += v == tn ? 1 : 0;
+        rest = (v != tn && v < rest) ? v : rest;
+    }
     c = block_sum_i64(c, red);
+    rest = block_min_i64(rest, red);
+    const bool frozen = tn > plan->t_limit;
     if (threadIdx.x == 0) {
         gcnt[blockIdx.x] = c;
+        gmin_next[blockIdx.x] = frozen ? gmin[blockIdx.x] : rest;
         if (blockIdx.x == 0) sel2[1] = tn;
     }
-    if (tn > plan->t_limit) return;
+    if (frozen) return;
     for (int k = base + threadIdx.x; k < end; k += kSelWG) pack_one<PREC>(pa, k, tn);
 }
 
@@ -324,26 +337,28 @@ __global__ __launch_bounds__(kSelWG) void blk_write_plan_kernel(int n, int ch, i
     }
 }
 
+int blk_chunk_size(int n) { return blk_chunk(n); }
+
 int blk_scratch_words(int n) {
     const int ch = blk_chunk(n);
     return 2 * ((n + ch - 1) / ch);
 }
 
 hipError_t launch_blk_front(const PackArgs& pa, const int64_t* dt, int32_t* idx, int64_t* sel2, DevPlan* plan,
-                            int64_t* scratch, int per_blk, int tile_j, hipStream_t st) {
+                            int64_t* scratch, int64_t* gmin, int64_t* gmin_next, bool need_min, int per_blk,
+                            int tile_j, hipStream_t st) {
     const int n = pa.n;
     if (n <= 0) return hipErrorInvalidValue;
     const int ch = blk_chunk(n);
     const int G = (n + ch - 1) / ch;
-    int64_t* gmin = scratch;
-    int64_t* gcnt = scratch + G;
-    hipLaunchKernelGGL(blk_min_kernel, dim3(G), dim3(kSelWG), 0, st, n, ch, pa.t, dt, gmin);
+    int64_t* gcnt = scratch;
+    if (need_min) hipLaunchKernelGGL(blk_min_kernel, dim3(G), dim3(kSelWG), 0, st, n, ch, pa.t, dt, gmin);
     if (pa.prec == 0)
-        hipLaunchKernelGGL(blk_count_pack_kernel<0>, dim3(G), dim3(kSelWG), 0, st, ch, G, dt, gmin, gcnt, sel2,
-                           plan, pa);
+        hipLaunchKernelGGL(blk_count_pack_kernel<0>, dim3(G), dim3(kSelWG), 0, st, ch, G, dt, gmin, gmin_next, gcnt,
+                           sel2, plan, pa);
     else
-        hipLaunchKernelGGL(blk_count_pack_kernel<1>, dim3(G), dim3(kSelWG), 0, st, ch, G, dt, gmin, gcnt, sel2,
-                           plan, pa);
+        hipLaunchKernelGGL(blk_count_pack_kernel<1>, dim3(G), dim3(kSelWG), 0, st, ch, G, dt, gmin, gmin_next, gcnt,
+                           sel2, plan, pa);
     hipLaunchKernelGGL(blk_write_plan_kernel, dim3(G), dim3(kSelWG), 0, st, n, ch, G, pa.t, dt, gcnt, sel2, idx,
                        plan, per_blk, tile_j);
     return hipGetLastError();
@@ -426,7 +441,12 @@ __device__ __forceinline__ void correct_core(const CorrectArgs& a, int c, const 
         const double na = norm3(a1[0], a1[1], a1[2]), nj = norm3(j1[0], j1[1], j1[2]);
         const double n2 = norm3(b0, b1, b2), n3 = norm3(a3[0], a3[1], a3[2]);
         const double crit = sqrt(a.eta * (na * n2 + nj * nj) / (nj * n3 + n2 * n2));
-        a.dt[i] = block_level(crit, a.dt[i], tn, a.lmin, a.lmax);
+        const int64_t dtn = block_level(crit, a.dt[i], tn, a.lmin, a.lmax);
+        a.dt[i] = dtn;
+        // the next block time of this particle joins its chunk's minimum
+        // (ticks are non-negative, so the unsigned minimum is the minimum)
+        if (a.gmin_next)
+            atomicMin((unsigned long long*)&a.gmin_next[i / a.gch], (unsigned long long)(tn + dtn));
     }
 }
 

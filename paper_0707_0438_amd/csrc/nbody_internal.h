@@ -187,15 +187,25 @@ struct CorrectArgs {
     float4* pack_next;
     int64_t tn_next;
     int pack_prec;
+    // Block steps: each corrected particle's new t + dt lowers the minimum of
+    // its chunk of gch particles in gmin_next (NULL: not kept).
+    int64_t* gmin_next;
+    int gch;
 };
 hipError_t launch_correct(const CorrectArgs& a, hipStream_t st);
 
 // Block-step front end: selection, prediction/packing of all j to the block
 // time, and the device plan (see hermite.hip).  pa.t and pa.n give the
-// ticks and count; scratch holds blk_scratch_words(n) int64 words.
+// ticks and count.  The particles fall into chunks of blk_chunk_size(n);
+// gmin and gmin_next hold one int64 per chunk (blk_scratch_words(n) / 2):
+// this step's chunk minima of t + dt (computed first when need_min) and the
+// next step's, which the corrector completes (CorrectArgs.gmin_next).
+// scratch holds blk_scratch_words(n) / 2 int64 words.
+int blk_chunk_size(int n);
 int blk_scratch_words(int n);
 hipError_t launch_blk_front(const PackArgs& pa, const int64_t* dt, int32_t* idx, int64_t* sel2, DevPlan* plan,
-                            int64_t* scratch, int per_blk, int tile_j, hipStream_t st);
+                            int64_t* scratch, int64_t* gmin, int64_t* gmin_next, bool need_min, int per_blk,
+                            int tile_j, hipStream_t st);
 // Block steps: split reduce (when the plan has S > 1) fused with the corrector.
 // With r.plan NULL the block is particles 0 .. r.ni-1 and the split is r.S.
 hipError_t launch_blk_reduce_correct(const ReduceArgs& r, const CorrectArgs& ca, int grid, hipStream_t st);
