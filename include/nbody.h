@@ -264,7 +264,9 @@ int nbody_force_vjp_self(nbody_ctx *ctx, hipStream_t stream, nbody_prec prec, do
  * starting from (x0, v0) = P0 with a, j evaluated there.  x_out, v_out:
  * device float64 [3][n].  ckpt: device buffer of nbody_shared_ckpt_bytes
  * bytes (or NULL) that receives (x, v, a, j) before every ckpt_every-th
- * step, for nbody_shared_adjoint. */
+ * step, for nbody_shared_adjoint.  n is at most 715827882 ((2^31-1)/3: the
+ * [3][n] rows are indexed as one int32 range); NBODY_ERR_ARG beyond, and
+ * nbody_shared_ckpt_bytes returns -1. */
 int64_t nbody_shared_ckpt_bytes(int64_t n, int nsteps, int ckpt_every);
 int nbody_shared_run(nbody_ctx *ctx, hipStream_t stream, nbody_prec prec, double G, double eps,
                      double dt, int nsteps, int64_t n, nbody_src P0, double *x_out, double *v_out,

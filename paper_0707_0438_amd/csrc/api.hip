@@ -21,6 +21,8 @@ using namespace nb;
 namespace {
 
 constexpr int64_t kMaxN = 2147483647LL;
+// The differentiable run's elementwise kernels index [3][n] rows as one int32 range.
+constexpr int64_t kMaxShared = kMaxN / 3;
 
 struct DevBuf {
     void* p = nullptr;
@@ -1383,13 +1385,15 @@ static int check_shared(nbody_ctx* c, nbody_prec prec, double G, double eps, dou
     if (int rc = check_common(c, prec, G, eps)) return rc;
     if (!(dt > 0.0) || !isfinite(dt)) return set_err(c, NBODY_ERR_ARG, "dt must be positive and finite");
     if (nsteps < 0) return set_err(c, NBODY_ERR_ARG, "nsteps must be >= 0");
-    if (n < 1 || n > kMaxN) return set_err(c, NBODY_ERR_ARG, "n must be in [1, 2^31-1]");
+    if (n < 1 || n > kMaxShared)
+        return set_err(c, NBODY_ERR_ARG, "n must be in [1, %lld] (3n vector entries are indexed in int32)",
+                       (long long)kMaxShared);
     if (every < 1) return set_err(c, NBODY_ERR_ARG, "ckpt_every must be >= 1");
     return NBODY_OK;
 }
 
 int64_t nbody_shared_ckpt_bytes(int64_t n, int nsteps, int every) {
-    if (n < 1 || nsteps < 0 || every < 1) return -1;
+    if (n < 1 || n > kMaxShared || nsteps < 0 || every < 1) return -1;
     const int64_t nseg = (nsteps + every - 1) / every;
     return std::max<int64_t>(nseg, 1) * 12 * n * (int64_t)sizeof(double);
 }

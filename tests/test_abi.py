@@ -153,6 +153,12 @@ def test_other_entry_points_validate(hostctx):
     assert L.nbody_hermite_create(h, C.byref(hp), 100, C.byref(o4)) == -1
     assert L.nbody_hermite_create(h, C.byref(hp), 100, C.byref(o)) == -4
     assert L.nbody_hermite_step(None, None, None, None) == -1
+    # the differentiable run indexes [3][n] rows in int32: n <= (2^31 - 1) / 3
+    assert L.nbody_shared_ckpt_bytes(715827882, 8, 8) == 12 * 8 * 715827882
+    assert L.nbody_shared_ckpt_bytes(715827883, 8, 8) == -1
+    P = nb.Src(*([None] * 7))
+    assert L.nbody_shared_run(h, None, 1, 1.0, 0.01, 0.01, 4, 715827883, P, None, None, None, 1) == -1
+    assert "715827882" in hostctx.last_error()
     assert L.nbody_destroy(None) == 0
 
 
