@@ -2,10 +2,13 @@
 """Throughput benchmark: one Hermite step of a 2^20-body Plummer sphere with
 every particle active, on one MI355X.
 
-A step is one pass of the whole hot path: active-block selection on integer
-ticks, float64 prediction of all particles and packing to the device
-layout, the O(N^2) pairwise acceleration/jerk/potential kernel, and the
-float64 corrector.  Inputs are resident in HBM before the timed region.
+A step is one pass of the hot path with every particle due (a shared step
+of 2^-10, so the block is all N particles in order and needs no selection
+pass): the O(N^2) pairwise acceleration/jerk/potential kernel, then the
+float64 corrector fused with the float64 prediction of every particle to
+the next step and its packing into the device layout.  The block-step form
+(integer selection, plan, split) is timed in the block_steps section.
+Inputs are resident in HBM before the timed region.
 
 Prints ONE JSON line (rank 0, N = 1):
   value     whole-job interactions per second (Ginteractions/s), N^2 per step
@@ -493,8 +496,8 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": "plummer1m_force: equal-mass Plummer sphere N=2^20 (seeded AHW sampling), "
-                        "eps=1e-4, all particles active; one step = block select + f64 predict/pack "
-                        "+ pairwise acc/jerk/pot + f64 Hermite corrector (shared dt 2^-10)",
+                        "eps=1e-4, all particles active; one step = pairwise acc/jerk/pot + f64 Hermite "
+                        "corrector fused with the f64 predict/pack of the next step (shared dt 2^-10)",
             "n": n, "eps": eps, "G": 1.0,
             "prec": "ds_comp" if args.prec == "ds" else "fp32",
             "tile": r["tile"],
