@@ -52,7 +52,7 @@ enum {
     NBODY_ERR_ARG = -1,          /* invalid argument (NULL, size, eps, alignment) */
     NBODY_ERR_NOMEM = -2,        /* device or host allocation failed */
     NBODY_ERR_DEVICE = -3,       /* HIP runtime error (launch, copy, fault) */
-    NBODY_ERR_UNSUPPORTED = -4,  /* valid request this build does not serve */
+    NBODY_ERR_UNSUPPORTED = -4,  /* valid request the library does not serve */
     NBODY_ERR_STATE = -5         /* object used out of order */
 };
 
