@@ -293,6 +293,55 @@ def test_salpeter64k_full_size_short_interval(ctx):
     assert abs((ek + ep - e0) / e0) < 1e-6
 
 
+def test_salpeter64k_statistics_against_oracle(ctx):
+    """The block-step workload at full size to t = 1/8 (about 3700 block
+    steps) against the float64 oracle's run of the same interval, whose
+    statistics tests/golden/make_salpeter64k_stats.py stored (the oracle takes
+    minutes).  Trajectories of two correct integrators part, so the DS run is
+    held to the oracle's block count, active count, energy error, census of
+    step levels and conservation of momentum and angular momentum; plain FP32
+    is reported beside it (its rounding noise changes the step choices)."""
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(__file__), "golden", "salpeter64k_oracle_stats.json")) as f:
+        g = json.load(f)
+    p = ics.workload("salpeter64k_block")
+    T = g["t_end_ticks"]
+    ref_levels = {int(k): v for k, v in g["end"]["levels"].items()}
+    L0 = np.array(g["angular_momentum_0"])
+    dL_ref = np.linalg.norm(np.array(g["end"]["angular_momentum"]) - L0)
+    for prec in ("ds", "fp32"):
+        h = ctx.hermite(p.n, eps=1e-3, eta=0.02, dt_min_log2=-20, dt_max_log2=-3, prec=prec)
+        h.set_state(dev(p.pos), dev(p.vel), dev(p.mass))
+        ek, ep = h.energy()
+        e0 = ek + ep
+        assert e0 == pytest.approx(g["E0"], rel=1e-6)
+        st = h.advance(T)
+        s = gpu_state(h)
+        ek, ep = h.energy()
+        de = (ek + ep - e0) / e0
+        assert np.all(s["t"] == T)
+        lv, cnt = np.unique(np.log2(s["dt"] / TICKS).astype(int), return_counts=True)
+        levels = dict(zip(lv.tolist(), cnt.tolist()))
+        tv = sum(abs(levels.get(k, 0) - ref_levels.get(k, 0)) for k in set(levels) | set(ref_levels)) / 2 / p.n
+        P = np.linalg.norm((p.mass * s["v"]).sum(axis=1))
+        L = (p.mass * np.cross(s["x"].T, s["v"].T).T).sum(axis=1)
+        dL = np.linalg.norm(L - L0)
+        print(f"{prec}: steps {st['steps']} (oracle {g['block_steps']}), active {st['sum_active']} "
+              f"(oracle {g['sum_active']}), dE/E {de:.3e} (oracle {g['end']['dE_over_E']:.3e}), "
+              f"level census distance {tv:.4f}, |P| {P:.2e} (oracle {g['end']['momentum']:.2e}), "
+              f"|dL| {dL:.2e} (oracle {dL_ref:.2e})", flush=True)
+        assert abs(de) < 1e-6
+        if prec == "ds":
+            assert abs(st["steps"] - g["block_steps"]) <= 0.03 * g["block_steps"]
+            assert abs(st["sum_active"] - g["sum_active"]) <= 0.03 * g["sum_active"]
+            assert abs(de - g["end"]["dE_over_E"]) < 1e-7
+            assert tv < 0.03
+            assert P < 5 * g["end"]["momentum"]
+            assert dL < 5 * dL_ref
+        h.close()
+
+
 @pytest.mark.parametrize("prec", ["ds", "fp32"])
 def test_shared_steps_unsoftened_kepler(ctx, prec):
     """The e = 0.5 two-body orbit with eps = 0 and shared steps of 2^-8 to
