@@ -81,10 +81,12 @@ typedef struct {
 
 /* Launch shape of the pairwise kernel (also the autotuner's search space).
  *  tile_j: j-particles per tile (staged in LDS when jsrc = 0; the interval
- *          between compensated folds when jsrc = 1): 64, 128, 256
- *          (jsrc = 1: 128).
+ *          between compensated folds when jsrc = 1): 64, 128, 256, and 16
+ *          or 32 with ipt 1 and wg 64 or 128 (short sweeps for small j
+ *          sets); jsrc = 1: 128.
  *  ipt:    i-particles held in registers per lane, one of 1, 2, 4.
- *  wg:     work-group size in lanes: 128 or 256 (jsrc = 1: 64 or 256).
+ *  wg:     work-group size in lanes: 128 or 256 (jsrc = 1: 64 or 256;
+ *          16- and 32-record tiles: 64 or 128).
  *  split:  number of j-ranges the j set is cut into (>= 1; 0 = choose
  *          from the shape); partial sums are reduced in float64 in fixed
  *          order (Section 3.2).

@@ -169,12 +169,19 @@ static int choose_split(int64_t ni, int64_t nj, const nbody_tile& t) {
 // Default launch shape when neither an override nor a tuned entry exists:
 // the fastest shape of the MI355X sweep at 2^20 x 2^20 (one i per lane,
 // 256-record LDS tiles, software-pipelined LDS reads) for large problems,
-// 64-record tiles for small ones (more j-ranges to spread over the CUs).
-static nbody_tile default_tile(int prec, int64_t ni, int64_t nj) {
+// 64-record tiles for small ones (more j-ranges to spread over the CUs), and
+// for the smallest j sets (latency-bound: the time is one work-group's
+// sweep) 32- or 16-record tiles in one-wave work-groups.  short_tiles: the
+// evaluation kind has those shapes.
+static nbody_tile default_tile(int prec, int64_t ni, int64_t nj, bool short_tiles = true) {
     nbody_tile t;
     const bool large = (double)ni * (double)nj >= 4294967296.0;
     t.tile_j = large ? 256 : 64;
     t.wg = large ? 256 : 128;
+    if (!large && short_tiles && nj <= 2048) {
+        t.tile_j = nj <= 512 ? 16 : 32;
+        t.wg = 64;
+    }
     t.ipt = 1;
     t.split = 0;
     t.jsrc = 0;
@@ -188,7 +195,7 @@ static nbody_tile default_tile(int prec, int64_t ni, int64_t nj) {
 // evaluations: the fastest shapes of the MI355X sweep at 2^20 x 2^20; small
 // problems take the small default shape.
 static nbody_tile default_tile_kind(int kind, int prec, int64_t ni, int64_t nj) {
-    nbody_tile t = default_tile(prec, ni, nj);
+    nbody_tile t = default_tile(prec, ni, nj, kind == 0);
     if ((double)ni * (double)nj < 4294967296.0) return t;
     if (kind == 1 && prec == 1) {
         t.tile_j = 128;

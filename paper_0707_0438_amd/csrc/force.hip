@@ -588,6 +588,9 @@ static const Variant kVariants[] = {
     NB_X(0, 1, 256, 256, 102, 0), NB_X(0, 1, 256, 256, 104, 0), NB_X(0, 2, 256, 256, 101, 0),
     NB_X(1, 1, 256, 256, 102, 0), NB_X(1, 1, 256, 256, 104, 0), NB_X(1, 2, 256, 256, 101, 0),
     NB_X(1, 1, 128, 256, 102, 0), NB_X(1, 1, 256, 128, 102, 0),
+    // short tiles for small, latency-bound sets (more j-ranges, shorter sweeps)
+    NB_X(0, 1, 16, 64, 4, 0), NB_X(0, 1, 32, 64, 4, 0), NB_X(0, 1, 16, 128, 4, 0), NB_X(0, 1, 32, 128, 4, 0),
+    NB_X(1, 1, 16, 64, 4, 0), NB_X(1, 1, 32, 64, 4, 0), NB_X(1, 1, 16, 128, 4, 0), NB_X(1, 1, 32, 128, 4, 0),
     // unsoftened (eps = 0) path: one shape per precision
     NB_V(0, 1, 128, 256, true), NB_V(0, 2, 128, 256, true),
     NB_V(1, 1, 128, 256, true), NB_V(1, 2, 128, 256, true),

@@ -69,6 +69,8 @@ def test_every_launch_shape_and_split(ctx, prec):
     S = dev(np.arange(p.n, dtype=np.int32))
     shapes = [(tj, ipt, wg, 0, 0, 0) for tj in (64, 128, 256) for ipt in (1, 2, 4) for wg in (128, 256)]
     shapes += [(128, ipt, wg, 1, 0, 0) for ipt in (1, 2, 4) for wg in (64, 256)]
+    # short tiles for small sets
+    shapes += [(tj, 1, wg, 0, 0, 0) for tj in (16, 32) for wg in (64, 128)]
     # unroll / occupancy / software-pipelined variants
     shapes += [(256, 1, 256, 0, 2, 0), (256, 1, 256, 0, 8, 0), (256, 1, 256, 0, 4, 6), (256, 1, 256, 0, 4, 8),
                (256, 2, 256, 0, 1, 0), (256, 2, 256, 0, 2, 0), (256, 2, 256, 0, 2, 5), (128, 2, 256, 0, 2, 4),
@@ -260,7 +262,7 @@ def test_autotune_cache_timing_and_reserve(tmp_path):
     try:
         c.reserve(4096, 4096)
         tile, ms = c.autotune(X, V, X, V, M, 0.01, prec="ds", reps=1)
-        assert ms > 0 and tile["tile_j"] in (64, 128, 256) and tile["ipt"] in (1, 2, 4)
+        assert ms > 0 and tile["tile_j"] in (16, 32, 64, 128, 256) and tile["ipt"] in (1, 2, 4)
         lines = [json.loads(ln) for ln in open(cache) if ln.strip()]
         assert len(lines) >= 1
         got = c.get_tile(3000, 3000, "ds")
