@@ -801,9 +801,6 @@ int nbody_hermite_set_state(nbody_hermite* h, hipStream_t st, nbody_src P) {
     return NBODY_OK;
 }
 
-// Shape of the plan-driven pairwise launch used for block steps (blocks are
-// usually small; the device decides the split from the block size).
-constexpr int kBlkTile = 64, kBlkWG = 128, kBlkIPT = 1, kBlkGrid = 2048;
 
 static int plan_reset(nbody_hermite* h, hipStream_t st, int64_t t_limit) {
     DevPlan p{};
@@ -950,8 +947,9 @@ static int hermite_enqueue_block(nbody_hermite* h, hipStream_t st) {
     int64_t* gmin_next = h->gmin2 + (size_t)(h->gpar ^ 1) * G;
     const bool need_min = !h->gmin_ok;
     h->gmin_ok = false;   // until every launch of this step is in
+    const bool eps0 = h->o.eps == 0.0;
     hipError_t e = launch_blk_front(pa, h->dt, h->idx, h->sel2, h->plan, (int64_t*)c->sel.p + 2, gmin, gmin_next,
-                                    need_min, kBlkWG * kBlkIPT, kBlkTile, st);
+                                    need_min, !eps0, st);
     if (e != hipSuccess) return hip_err(c, e, "select/pack/plan launch");
     ForceArgs a{};
     a.ipack = (const float4*)c->jpack.p;
@@ -966,8 +964,7 @@ static int hermite_enqueue_block(nbody_hermite* h, hipStream_t st) {
     for (int q = 0; q < 7; ++q) a.out[q] = h->f[q];
     a.part = (float2*)c->part.p;
     a.plan = h->plan;
-    const bool eps0 = h->o.eps == 0.0;
-    e = launch_force_plan(p, kBlkIPT, kBlkTile, kBlkWG, eps0, kBlkGrid, a, st);
+    e = launch_force_plan(p, eps0, a, st);
     if (e != hipSuccess) return hip_err(c, e, "force launch");
     ReduceArgs r{};
     r.ni = n;
@@ -999,8 +996,9 @@ static int block_buffers(nbody_hermite* h) {
     const int64_t n = h->n;
     const int words = std::max(select_scratch_words((int)n), blk_scratch_words((int)n));
     int rc = dev_alloc(c, c->sel, (2 + (size_t)words) * sizeof(int64_t));
-    // partials: S * n_act <= (2048 + nb) * per_blk <= 2049 * per_blk + n
-    if (!rc) rc = dev_alloc(c, c->part, sizeof(float2) * 7 * ((size_t)2049 * kBlkWG * kBlkIPT + (size_t)n));
+    // partials: S * n_act <= (2048 + nb) * per_blk <= 2049 * per_blk + n for either shape
+    const size_t per_blk = (size_t)std::max(kBlkSmallWG, kBlkBigWG);
+    if (!rc) rc = dev_alloc(c, c->part, sizeof(float2) * 7 * (2049 * per_blk + (size_t)n));
     if (!rc) rc = dev_alloc(c, c->jpack, sizeof(float4) * rec_words((int)h->o.prec) * (size_t)n);
     return rc;
 }

@@ -321,13 +321,14 @@ __global__ __launch_bounds__(WG) void force_kernel_kind(ForceArgs a) {
 
 // Plan-driven launch for block steps: the block size and the split come
 // from the device plan; a fixed grid strides over the nb x S (i-block,
-// j-range) pairs.  Each pair runs exactly the code of force_kernel.
-template <int PREC, int IPT, int TJ, int WG, bool EPS0>
+// j-range) pairs.  Each pair runs exactly the code of force_kernel.  SHAPE
+// >= 0: only when the plan picked that shape.
+template <int PREC, int IPT, int TJ, int WG, bool EPS0, int UNR = 4, int SHAPE = -1>
 __global__ __launch_bounds__(WG) void force_kernel_plan(ForceArgs a) {
     __shared__ float4 sh[2][TJ * Rec<PREC>::R];
     const DevPlan* pl = a.plan;
     const int n = (int)pl->n_act;
-    if (n <= 0) return;
+    if (n <= 0 || (SHAPE >= 0 && pl->shape != SHAPE)) return;
     const int nb = pl->nb, S = pl->S;
     ForceArgs b = a;
     b.ni = n;
@@ -337,7 +338,8 @@ __global__ __launch_bounds__(WG) void force_kernel_plan(ForceArgs a) {
         const int ib = v % nb, s = v / nb;
         const int jb = s * b.jchunk;
         const int je = min(b.nj, jb + b.jchunk);
-        force_block<PREC, IPT, TJ, WG, EPS0>(b, sh, ib * (WG * IPT), n, jb, je, b.eps2, s);
+        force_block<PREC, IPT, TJ, WG, EPS0, false, (UNR >= 100 ? UNR - 100 : UNR), (UNR >= 100)>(
+            b, sh, ib * (WG * IPT), n, jb, je, b.eps2, s);
     }
 }
 
@@ -631,21 +633,25 @@ hipError_t launch_force_batched(int prec, int ipt, int tj, int wg, int grid, con
 int force_variant_count() { return (int)(sizeof(kVariants) / sizeof(kVariants[0])); }
 
 // plan-driven shapes (block steps)
-bool force_plan_variant_exists(int prec, int ipt, int tj, int wg) {
-    return (prec == 0 || prec == 1) && ipt == 1 && tj == 64 && wg == 128;
+template <int PREC>
+static void launch_plan_pair(bool eps0, const ForceArgs& a, hipStream_t st) {
+    if (eps0) {
+        hipLaunchKernelGGL((force_kernel_plan<PREC, 1, kBlkSmallTile, kBlkSmallWG, true>), dim3(kBlkGrid),
+                           dim3(kBlkSmallWG), 0, st, a);
+        return;
+    }
+    hipLaunchKernelGGL((force_kernel_plan<PREC, 1, kBlkSmallTile, kBlkSmallWG, false, 4, 0>), dim3(kBlkGrid),
+                       dim3(kBlkSmallWG), 0, st, a);
+    if (kBlkBigMin > 0)
+        hipLaunchKernelGGL((force_kernel_plan<PREC, 1, kBlkBigTile, kBlkBigWG, false, 102, 1>), dim3(kBlkGrid),
+                           dim3(kBlkBigWG), 0, st, a);
 }
 
-hipError_t launch_force_plan(int prec, int ipt, int tj, int wg, bool eps0, int grid, const ForceArgs& a,
-                             hipStream_t st) {
-    if (!force_plan_variant_exists(prec, ipt, tj, wg)) return hipErrorInvalidValue;
-    if (prec == 0 && !eps0)
-        hipLaunchKernelGGL((force_kernel_plan<0, 1, 64, 128, false>), dim3(grid), dim3(128), 0, st, a);
-    else if (prec == 0)
-        hipLaunchKernelGGL((force_kernel_plan<0, 1, 64, 128, true>), dim3(grid), dim3(128), 0, st, a);
-    else if (!eps0)
-        hipLaunchKernelGGL((force_kernel_plan<1, 1, 64, 128, false>), dim3(grid), dim3(128), 0, st, a);
+hipError_t launch_force_plan(int prec, bool eps0, const ForceArgs& a, hipStream_t st) {
+    if (prec == 0)
+        launch_plan_pair<0>(eps0, a, st);
     else
-        hipLaunchKernelGGL((force_kernel_plan<1, 1, 64, 128, true>), dim3(grid), dim3(128), 0, st, a);
+        launch_plan_pair<1>(eps0, a, st);
     return hipGetLastError();
 }
 

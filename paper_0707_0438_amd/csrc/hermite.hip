@@ -281,7 +281,7 @@ __global__ __launch_bounds__(kSelWG) void blk_write_plan_kernel(int n, int ch, i
                                                                 const int64_t* __restrict__ gcnt,
                                                                 int64_t* __restrict__ sel2,
                                                                 int32_t* __restrict__ idx, DevPlan* plan,
-                                                                int per_blk, int tile_j) {
+                                                                int big_ok) {
     __shared__ int64_t red[kSelWG / 64];
     __shared__ int wsum[kSelWG / 64];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -323,8 +323,14 @@ __global__ __launch_bounds__(kSelWG) void blk_write_plan_kernel(int n, int ch, i
             plan->n_act = 0;
             plan->frozen = 1;
         } else {
+            // large blocks take the large direct evaluations' shape
+            const int big = big_ok && kBlkBigMin > 0 && total >= kBlkBigMin;
             int nb, S, jc;
-            split_plan(total, n, per_blk, tile_j, 0, &nb, &S, &jc, kBlkMinTiles);
+            if (big)
+                split_plan(total, n, kBlkBigWG, kBlkBigTile, 0, &nb, &S, &jc, 1);
+            else
+                split_plan(total, n, kBlkSmallWG, kBlkSmallTile, 0, &nb, &S, &jc, kBlkMinTiles);
+            plan->shape = big;
             plan->n_act = total;
             plan->t_next = tn;
             plan->nb = nb;
@@ -345,8 +351,8 @@ int blk_scratch_words(int n) {
 }
 
 hipError_t launch_blk_front(const PackArgs& pa, const int64_t* dt, int32_t* idx, int64_t* sel2, DevPlan* plan,
-                            int64_t* scratch, int64_t* gmin, int64_t* gmin_next, bool need_min, int per_blk,
-                            int tile_j, hipStream_t st) {
+                            int64_t* scratch, int64_t* gmin, int64_t* gmin_next, bool need_min, bool big_ok,
+                            hipStream_t st) {
     const int n = pa.n;
     if (n <= 0) return hipErrorInvalidValue;
     const int ch = blk_chunk(n);
@@ -360,7 +366,7 @@ hipError_t launch_blk_front(const PackArgs& pa, const int64_t* dt, int32_t* idx,
         hipLaunchKernelGGL(blk_count_pack_kernel<1>, dim3(G), dim3(kSelWG), 0, st, ch, G, dt, gmin, gmin_next, gcnt,
                            sel2, plan, pa);
     hipLaunchKernelGGL(blk_write_plan_kernel, dim3(G), dim3(kSelWG), 0, st, n, ch, G, pa.t, dt, gcnt, sel2, idx,
-                       plan, per_blk, tile_j);
+                       plan, big_ok ? 1 : 0);
     return hipGetLastError();
 }
 

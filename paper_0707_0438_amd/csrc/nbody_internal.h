@@ -62,7 +62,27 @@ struct DevPlan {
     int64_t t_last;             // latest block time taken
     int64_t t_limit;            // end time of the current advance (ticks)
     int nb, S, jchunk, frozen;  // launch geometry; frozen = the gate stopped a step
+    int shape, pad_;            // launch shape of the block: 0 small, 1 large (see below)
 };
+
+// Launch shapes of the plan-driven pairwise kernel (block steps).  Small
+// blocks are latency-bound and take short j-ranges in small work-groups;
+// blocks of at least kBlkBigMin particles take the shape of the large
+// direct evaluations.  Each step launches both kernels and the one whose
+// shape the plan did not pick returns at once.
+#ifndef NB_BLK_SMALL_TJ
+#define NB_BLK_SMALL_TJ 64
+#endif
+#ifndef NB_BLK_SMALL_WG
+#define NB_BLK_SMALL_WG 128
+#endif
+#ifndef NB_BLK_BIG_MIN
+#define NB_BLK_BIG_MIN 2048
+#endif
+constexpr int kBlkSmallTile = NB_BLK_SMALL_TJ, kBlkSmallWG = NB_BLK_SMALL_WG;
+constexpr int kBlkBigTile = 256, kBlkBigWG = 256;
+constexpr int kBlkBigMin = NB_BLK_BIG_MIN;   // 0: the large shape is never used
+constexpr int kBlkGrid = 2048;               // work-groups of each plan-driven launch
 
 // Arguments of the pairwise kernel (passed by value).
 struct ForceArgs {
@@ -118,8 +138,9 @@ hipError_t launch_lf_kick_drift_pack(int prec, int n, double* x, double* v, cons
                                      double h, double dt, float4* out, hipStream_t st);
 hipError_t launch_lf_kick(int n, double* v, const double* acc, double h, hipStream_t st);
 // Plan-driven launches (block sizes known only on the device).
-bool force_plan_variant_exists(int prec, int ipt, int tile_j, int wg);
-hipError_t launch_force_plan(int prec, int ipt, int tile_j, int wg, bool eps0, int grid, const ForceArgs& a,
+// Plan-driven pairwise launches of one block step (both shapes; eps0: the
+// small shape only).
+hipError_t launch_force_plan(int prec, bool eps0, const ForceArgs& a,
                              hipStream_t st);
 
 // ---- batched clusters ----
@@ -200,12 +221,13 @@ hipError_t launch_correct(const CorrectArgs& a, hipStream_t st);
 // gmin and gmin_next hold one int64 per chunk (blk_scratch_words(n) / 2):
 // this step's chunk minima of t + dt (computed first when need_min) and the
 // next step's, which the corrector completes (CorrectArgs.gmin_next).
-// scratch holds blk_scratch_words(n) / 2 int64 words.
+// scratch holds blk_scratch_words(n) / 2 int64 words.  big_ok: the plan may
+// pick the large launch shape.
 int blk_chunk_size(int n);
 int blk_scratch_words(int n);
 hipError_t launch_blk_front(const PackArgs& pa, const int64_t* dt, int32_t* idx, int64_t* sel2, DevPlan* plan,
-                            int64_t* scratch, int64_t* gmin, int64_t* gmin_next, bool need_min, int per_blk,
-                            int tile_j, hipStream_t st);
+                            int64_t* scratch, int64_t* gmin, int64_t* gmin_next, bool need_min, bool big_ok,
+                            hipStream_t st);
 // Block steps: split reduce (when the plan has S > 1) fused with the corrector.
 // With r.plan NULL the block is particles 0 .. r.ni-1 and the split is r.S.
 hipError_t launch_blk_reduce_correct(const ReduceArgs& r, const CorrectArgs& ca, int grid, hipStream_t st);
