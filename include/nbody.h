@@ -385,8 +385,10 @@ int nbody_hermite_get_state(nbody_hermite *h, hipStream_t stream, nbody_src P_ou
 int nbody_hermite_step(nbody_hermite *h, hipStream_t stream, int64_t *n_active, int64_t *t_ticks);
 
 /* Block steps until the next block time would exceed t_end_ticks.  With
- * block steps the block size, the launch geometry of the pairwise kernel
- * (i-blocks, j-ranges) and the end-time gate are decided on the device, by
+ * block steps the block size, the launch shape and geometry of the pairwise
+ * kernel (short tiles for small blocks, the large evaluations' shape from
+ * 2048 particles; i-blocks, j-ranges) and the end-time gate are decided on
+ * the device, by
  * one thread at the end of the selection pass; steps are enqueued in growing
  * chunks (up to 64) and the host reads the plan's statistics once per chunk
  * (so the call returns with `stream` synchronised).  A step whose
