@@ -705,7 +705,8 @@ int nbody_hermite_create(nbody_ctx* c, nbody_hermite** hp, int64_t n, const nbod
     const size_t bytes = (13 + 7 + 6) * r256(sizeof(double) * nn) + 2 * r256(sizeof(int64_t) * nn) +
                          r256(sizeof(int32_t) * nn) + r256(sizeof(int64_t) * 2) + r256(sizeof(int64_t)) +
                          r256(sizeof(double) * 2) + r256(sizeof(DevPlan)) +
-                         r256(sizeof(float4) * kRecDS * nn) + r256(sizeof(int64_t) * blk_scratch_words((int)n));
+                         (o->shared_dt_log2 != 0 ? r256(sizeof(float4) * kRecDS * nn) : 0) +
+                         r256(sizeof(int64_t) * blk_scratch_words((int)n));
     ++c->alloc_count;
     if (c->fail_alloc_at > 0 && c->alloc_count == c->fail_alloc_at) {
         delete h;
@@ -733,7 +734,7 @@ int nbody_hermite_create(nbody_ctx* c, nbody_hermite** hp, int64_t n, const nbod
     h->tnow = (int64_t*)take(sizeof(int64_t));
     h->e2 = (double*)take(sizeof(double) * 2);
     h->plan = (DevPlan*)take(sizeof(DevPlan));
-    h->spack = (float4*)take(sizeof(float4) * kRecDS * nn);
+    if (o->shared_dt_log2 != 0) h->spack = (float4*)take(sizeof(float4) * kRecDS * nn);   // shared steps only
     h->gmin2 = (int64_t*)take(sizeof(int64_t) * blk_scratch_words((int)n));
     *hp = h;
     return NBODY_OK;
