@@ -219,7 +219,13 @@ hipError_t launch_select(int n, const int64_t* t, const int64_t* dt, int32_t* id
 constexpr int kBlkGroups = 256;
 // Block steps split j down to this many tiles per range: small blocks are
 // latency-bound, so short j-ranges on many work-groups finish sooner.
+// Blocks of at most kBlkTinyMax particles (one i-block) go down to one tile
+// per range, and each work-group's sweep to a single tile.
 constexpr int kBlkMinTiles = 2;
+#ifndef NB_BLK_TINY_MAX
+#define NB_BLK_TINY_MAX 128
+#endif
+constexpr int kBlkTinyMax = NB_BLK_TINY_MAX;
 
 __host__ __device__ inline int blk_chunk(int n) {
     int ch = kSelWG;
@@ -329,7 +335,8 @@ __global__ __launch_bounds__(kSelWG) void blk_write_plan_kernel(int n, int ch, i
             if (big)
                 split_plan(total, n, kBlkBigWG, kBlkBigTile, 0, &nb, &S, &jc, 1);
             else
-                split_plan(total, n, kBlkSmallWG, kBlkSmallTile, 0, &nb, &S, &jc, kBlkMinTiles);
+                split_plan(total, n, kBlkSmallWG, kBlkSmallTile, 0, &nb, &S, &jc,
+                           total <= kBlkTinyMax ? 1 : kBlkMinTiles);
             plan->shape = big;
             plan->n_act = total;
             plan->t_next = tn;
@@ -490,6 +497,54 @@ __global__ __launch_bounds__(256) void blk_reduce_correct_kernel(ReduceArgs r, C
         return;
     }
     const int lane = threadIdx.x & 63;
+    if (n <= (int)gridDim.x && S > 64) {
+        // few particles, many ranges: a work-group per particle.  Thread k
+        // sums the ranges s = k, k + 256, ... in order; the lanes of a wave
+        // then combine by a fixed butterfly and the four waves in order.
+        __shared__ double wpart[4][6];
+        const int c = blockIdx.x;
+        if (c >= n) return;
+        const int tid = threadIdx.x, w = tid >> 6;
+        const float2* col = r.part + c;
+        const size_t qs = (size_t)n, rs = 7 * (size_t)n;
+        double f[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        int sp = tid;
+        for (; sp + 256 < S; sp += 512) {
+            float2 u[2][6];
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+#pragma unroll
+                for (int q = 0; q < 6; ++q) u[h][q] = col[(size_t)(sp + 256 * h) * rs + q * qs];
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+#pragma unroll
+                for (int q = 0; q < 6; ++q) {
+                    f[q] += (double)u[h][q].x;
+                    f[q] += (double)u[h][q].y;
+                }
+        }
+        for (; sp < S; sp += 256) {
+#pragma unroll
+            for (int q = 0; q < 6; ++q) {
+                const float2 u = col[(size_t)sp * rs + q * qs];
+                f[q] += (double)u.x;
+                f[q] += (double)u.y;
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+            for (int off = 32; off > 0; off >>= 1) f[q] += __shfl_xor(f[q], off);
+            if (lane == 0) wpart[w][q] = f[q];
+        }
+        __syncthreads();
+        if (tid == 0) {
+            double g[6];
+#pragma unroll
+            for (int q = 0; q < 6; ++q) g[q] = r.G * (((wpart[0][q] + wpart[1][q]) + wpart[2][q]) + wpart[3][q]);
+            correct_core(ca, c, g, g + 3);
+        }
+        return;
+    }
     const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
     for (int64_t w = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; w < n; w += nw) {
         const int c = (int)w;
