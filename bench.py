@@ -295,6 +295,33 @@ def kinds_timing(ctx, X, V, M, eps, prec, full_kernel_ms, reps=2):
     return out
 
 
+def shard_timing(ctx, X, V, M, eps, prec, full_kernel_ms, shards=8, reps=3):
+    """One GPU's share of an i-parallel evaluation over `shards` GPUs: the
+    first N/shards particles of the N = 2^20 system as i against all N as j
+    (self excluded by index), the shape each GPU would run.  Timed per
+    launch with HIP events on the launch stream."""
+    import torch
+    n = X.shape[1]
+    ni = n // shards
+    xi, vi = X[:, :ni].contiguous(), V[:, :ni].contiguous()
+    S = torch.arange(ni, dtype=torch.int32, device="cuda")
+    fn = lambda: ctx.force(xi, vi, X, V, M, eps, prec=prec, i_self=S)
+    fn()
+    torch.cuda.synchronize()
+    ctx.kernel_timing(True)
+    for _ in range(reps):
+        fn()
+    ms, launches = ctx.kernel_time()
+    ctx.kernel_timing(False)
+    ms /= max(launches, 1)
+    gint = float(ni) * n / (ms * 1e-3) / 1e9
+    return {"workload": f"plummer1m_force i-slice: the first {ni} of N={n} particles (eps={eps}) against all {n}, "
+                        f"one GPU's share of a {shards}-GPU i-parallel evaluation, {reps} launches",
+            "tile": ctx.get_tile(ni, n, prec), "kernel_ms": round(ms, 3), "Gint_s": round(gint, 1),
+            "pct_fp32_peak": round(100.0 * FLOPS_PER_INTERACTION * gint / 1e3 / FP32_PEAK_TFLOPS, 2),
+            "time_vs_full_kernel": round(ms / full_kernel_ms, 4)}
+
+
 def shared1k_timing(ctx, reps=5):
     """The N = 1024 shared-step workload (equal-mass Plummer, eps = 1/256,
     dt = 1/256 to t = 1/8, 32 steps): wall time per step (best of reps, state
@@ -429,8 +456,8 @@ def main():
     ap.add_argument("--block-run", action="store_true",
                     help="only run the Salpeter block-step workload (--n, --t-end) and print its JSON")
     ap.add_argument("--t-end", type=float, default=1.0)
-    ap.add_argument("--extras", default="batched,adjoint,kinds,block,shared1k",
-                    help="comma list of extra measurements (batched, adjoint, kinds, block, shared1k) or 'none'")
+    ap.add_argument("--extras", default="batched,adjoint,kinds,shard,block,shared1k",
+                    help="comma list of extra measurements (batched, adjoint, kinds, shard, block, shared1k) or 'none'")
     ap.add_argument("--report-every", type=float, default=0.0)
     args = ap.parse_args()
     if args.copy_calibration:
@@ -536,6 +563,9 @@ def main():
     if "kinds" in extras:
         log("[bench] force-only and nearest-neighbour evaluations")
         line["kinds"] = kinds_timing(ctx, X, V, M, eps, args.prec, k_ms)
+    if "shard" in extras:
+        log("[bench] one GPU's share of an 8-GPU i-parallel evaluation")
+        line["shard8"] = shard_timing(ctx, X, V, M, eps, args.prec, k_ms)
     if "block" in extras:
         log("[bench] block steps, Salpeter N=65536 to t=1/4")
         line["block_steps"] = block_run(65536, 0.25, ["ds", "fp32"], ctx=ctx, marks_out=False)
