@@ -88,8 +88,10 @@ typedef struct {
  *  wg:     work-group size in lanes: 128 or 256 (jsrc = 1: 64 or 256;
  *          16- and 32-record tiles: 64 or 128).
  *  split:  number of j-ranges the j set is cut into (>= 1; 0 = choose
- *          from the shape); partial sums are reduced in float64 in fixed
- *          order (Section 3.2).
+ *          from the shape and the sizes: enough work-groups to fill the
+ *          device, and for long evaluations at least 32768 work-groups,
+ *          each range keeping at least 64 tiles); partial sums are reduced
+ *          in float64 in fixed order (Section 3.2).
  *  jsrc:   0 = j records staged tile by tile in LDS (Section 3.1, Fig. 1);
  *          1 = j records read by wave-uniform loads through the scalar data
  *          cache (no LDS, no barrier).

@@ -159,11 +159,23 @@ static bool valid_tile(const nbody_tile& t) {
            force_variant_exists(1, t.ipt, t.tile_j, t.wg, t.jsrc, t.unroll, t.waves, false);
 }
 
-// Number of j-ranges for an i-list of ni against nj (see split_plan).
+// Number of j-ranges for an i-list of ni against nj (see split_plan).  Long
+// evaluations also split j: with at least kLongWG work-groups in all, the
+// last, partly filled round of resident work-groups is a small part of the
+// launch.  Each range keeps at least kLongTiles tiles, and the partials stay
+// below (kLongWG + i-blocks) x 56 B per i-block lane.  On MI355X at N = 2^20
+// this took the large DS evaluation from 749 to 726 ms (4096 i-blocks, 8
+// ranges), and 2^17 i against 2^20 j from 96 to 90 ms (64 ranges).
+constexpr int64_t kLongWG = 32768;
+constexpr int64_t kLongTiles = 64;
 static int choose_split(int64_t ni, int64_t nj, const nbody_tile& t) {
     int nb, S, jc;
     split_plan(ni, nj, t.wg * t.ipt, t.tile_j, 0, &nb, &S, &jc);
-    return S;
+    const int64_t per = (int64_t)t.wg * t.ipt;
+    const int64_t nbl = (ni + per - 1) / per;
+    int64_t Sl = nbl > 0 ? (kLongWG + nbl - 1) / nbl : 1;
+    Sl = std::min<int64_t>(Sl, nj / (kLongTiles * t.tile_j));
+    return (int)std::max<int64_t>(S, Sl);
 }
 
 // Default launch shape when neither an override nor a tuned entry exists:
