@@ -163,7 +163,7 @@ static bool valid_tile(const nbody_tile& t) {
 // evaluations also split j: with at least kLongWG work-groups in all, the
 // last, partly filled round of resident work-groups is a small part of the
 // launch.  Each range keeps at least kLongTiles tiles, and the partials stay
-// below (kLongWG + i-blocks) x 56 B per i-block lane.  On MI355X at N = 2^20
+// below (kLongWG + i-blocks) x (i per block) x 56 B.  On MI355X at N = 2^20
 // this took the large DS evaluation from 749 to 726 ms (4096 i-blocks, 8
 // ranges), and 2^17 i against 2^20 j from 96 to 90 ms (64 ranges).
 constexpr int64_t kLongWG = 32768;

@@ -498,9 +498,10 @@ __global__ __launch_bounds__(256) void blk_reduce_correct_kernel(ReduceArgs r, C
     }
     const int lane = threadIdx.x & 63;
     if (n <= (int)gridDim.x && S > 64) {
-        // few particles, many ranges: a work-group per particle.  Thread k
-        // sums the ranges s = k, k + 256, ... in order; the lanes of a wave
-        // then combine by a fixed butterfly and the four waves in order.
+        // few particles, many ranges: a work-group (256 threads, as launched)
+        // per particle.  Thread k sums the ranges s = k, k + 256, ... in
+        // order; the lanes of a wave then combine by a fixed butterfly and
+        // the four waves in order.
         __shared__ double wpart[4][6];
         const int c = blockIdx.x;
         if (c >= n) return;
