@@ -179,8 +179,9 @@ static int choose_split(int64_t ni, int64_t nj, const nbody_tile& t) {
 }
 
 // Default launch shape when neither an override nor a tuned entry exists:
-// the fastest shape of the MI355X sweep at 2^20 x 2^20 (one i per lane,
-// 256-record LDS tiles, software-pipelined LDS reads) for large problems,
+// the fastest shape of the MI355X sweep at 2^20 x 2^20 (256-record LDS
+// tiles, software-pipelined LDS reads; two i per lane for DS, one for plain
+// FP32) for large problems,
 // 64-record tiles for small ones (more j-ranges to spread over the CUs), and
 // for the smallest j sets (latency-bound: the time is one work-group's
 // sweep) 32- or 16-record tiles in one-wave work-groups.  short_tiles: the
@@ -194,12 +195,14 @@ static nbody_tile default_tile(int prec, int64_t ni, int64_t nj, bool short_tile
         t.tile_j = nj <= 512 ? 16 : 32;
         t.wg = 64;
     }
-    t.ipt = 1;
+    // DS at large sizes: two i per lane (with the long-evaluation split,
+    // 683 ms at 2^20 against 709-713 ms for one i per lane, same box);
+    // plain FP32 keeps one i per lane (578-580 ms against 594)
+    t.ipt = (large && prec == 1) ? 2 : 1;
     t.split = 0;
     t.jsrc = 0;
-    t.unroll = large ? 102 : 0;
+    t.unroll = large ? (prec == 1 ? 101 : 102) : 0;
     t.waves = 0;
-    (void)prec;
     return t;
 }
 
@@ -207,18 +210,9 @@ static nbody_tile default_tile(int prec, int64_t ni, int64_t nj, bool short_tile
 // evaluations: the fastest shapes of the MI355X sweep at 2^20 x 2^20; small
 // problems take the small default shape.
 static nbody_tile default_tile_kind(int kind, int prec, int64_t ni, int64_t nj) {
-    nbody_tile t = default_tile(prec, ni, nj, kind == 0);
-    if ((double)ni * (double)nj < 4294967296.0) return t;
-    if (kind == 1 && prec == 1) {
-        // two i per lane, pipelined: 421 ms at 2^20 against 440 ms for the
-        // 128-record one-i shape in a same-box sweep with the long split
-        t.ipt = 2;
-        t.unroll = 101;
-    } else if (kind == 2 && prec == 1) {
-        t.ipt = 2;
-        t.unroll = 101;
-    }
-    return t;
+    // the full evaluation's default (two i per lane for DS at large sizes) is
+    // also the fastest force-only and neighbour shape of the sweeps
+    return default_tile(prec, ni, nj, kind == 0);
 }
 
 static nbody_tile pick_tile(nbody_ctx* c, int prec, int64_t ni, int64_t nj) {
