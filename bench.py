@@ -35,6 +35,7 @@ FP32_PEAK_TFLOPS = 157.3            # MI355X FP32 vector peak (256 CU x 64 x 2 x
 PAPER_GINT_S = 1.0995116e12 / 279.4067 / 1e9   # 8800GTX, N = 2^20, Table 4 (context)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "force_ds_plummer1m_traffic.txt")
 FORCE_SRC = os.path.join(ROOT, "paper_0707_0438_amd", "csrc", "force.hip")
+LAUNCH_SRC = os.path.join(ROOT, "paper_0707_0438_amd", "csrc", "api.hip")
 
 
 def log(*a):
@@ -43,8 +44,8 @@ def log(*a):
 
 def traffic_per_launch(prec: str):
     """HBM bytes per launch of the pairwise kernel from the committed rocprofv3
-    counter summary, or None when it is missing or the kernel source changed
-    since the counters were taken."""
+    counter summary, or None when it is missing or the kernel source or the
+    launch-shape rules changed since the counters were taken."""
     if prec != "ds" or not os.path.exists(TRAFFIC_FILE):
         return None
     kv = {}
@@ -52,7 +53,10 @@ def traffic_per_launch(prec: str):
         if ":" in ln:
             k, v = ln.split(":", 1)
             kv[k.strip()] = v.strip()
-    sha = hashlib.sha256(open(FORCE_SRC, "rb").read()).hexdigest()
+    h = hashlib.sha256()
+    for src in (FORCE_SRC, LAUNCH_SRC):   # the kernels and the launch shapes they run in
+        h.update(open(src, "rb").read())
+    sha = h.hexdigest()
     if kv.get("kernel_source_sha256") != sha:
         return None
     try:
