@@ -34,6 +34,7 @@ FLOPS_PER_INTERACTION = 60          # acc + jerk + potential convention (Eq. 3, 
 FP32_PEAK_TFLOPS = 157.3            # MI355X FP32 vector peak (256 CU x 64 x 2 x 2 x 2.4 GHz)
 PAPER_GINT_S = 1.0995116e12 / 279.4067 / 1e9   # 8800GTX, N = 2^20, Table 4 (context)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "force_ds_plummer1m_traffic.txt")
+VALU_FILE = os.path.join(ROOT, "profiles", "force_plummer1m_valu_clock.txt")
 FORCE_SRC = os.path.join(ROOT, "paper_0707_0438_amd", "csrc", "force.hip")
 LAUNCH_SRC = os.path.join(ROOT, "paper_0707_0438_amd", "csrc", "api.hip")
 
@@ -42,27 +43,58 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def kernel_source_sha256() -> str:
+    """One sha256 over the pairwise kernels and the launch-shape rules they run
+    under; counter summaries record it and are used only while it matches."""
+    h = hashlib.sha256()
+    for src in (FORCE_SRC, LAUNCH_SRC):
+        h.update(open(src, "rb").read())
+    return h.hexdigest()
+
+
+def profile_keys(path):
+    """The `key: value` lines of a committed counter summary, or None when the
+    file is missing or was taken on other kernel sources."""
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for ln in open(path):
+        if ":" in ln:
+            k, v = ln.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_sha256") != kernel_source_sha256():
+        return None
+    return kv
+
+
 def traffic_per_launch(prec: str):
     """HBM bytes per launch of the pairwise kernel from the committed rocprofv3
     counter summary, or None when it is missing or the kernel source or the
     launch-shape rules changed since the counters were taken."""
-    if prec != "ds" or not os.path.exists(TRAFFIC_FILE):
-        return None
-    kv = {}
-    for ln in open(TRAFFIC_FILE):
-        if ":" in ln:
-            k, v = ln.split(":", 1)
-            kv[k.strip()] = v.strip()
-    h = hashlib.sha256()
-    for src in (FORCE_SRC, LAUNCH_SRC):   # the kernels and the launch shapes they run in
-        h.update(open(src, "rb").read())
-    sha = h.hexdigest()
-    if kv.get("kernel_source_sha256") != sha:
-        return None
+    kv = profile_keys(TRAFFIC_FILE) if prec == "ds" else None
     try:
-        return float(kv["traffic_bytes_per_launch"])
+        return float(kv["traffic_bytes_per_launch"]) if kv else None
     except (KeyError, ValueError):
         return None
+
+
+def executed_flops(prec: str, gint_s: float):
+    """Executed FP32 flop rate of the pairwise kernel: the flop per interaction
+    the VALU counters measured (ADD + MUL + TRANS + 2 FMA instructions x 64
+    lanes, per interaction; committed summary, used only while the kernel
+    sources match) times the measured interaction rate.  None otherwise."""
+    kv = profile_keys(VALU_FILE)
+    key = ("ds" if prec == "ds" else "fp32") + "_executed_flop_per_interaction"
+    try:
+        f = float(kv[key]) if kv else None
+    except (KeyError, ValueError):
+        f = None
+    if f is None:
+        return None
+    tf = f * gint_s / 1e3
+    return {"flop_per_interaction": f, "TFLOP_s": round(tf, 2),
+            "pct_fp32_peak": round(100.0 * tf / FP32_PEAK_TFLOPS, 2),
+            "source": os.path.relpath(VALU_FILE, ROOT)}
 
 
 def device_clock_ghz():
@@ -557,13 +589,20 @@ def main():
             "kernel_ms": round(o["kms"] / max(o["launches"], 1), 3),
             "pct_fp32_peak": round(100.0 * FLOPS_PER_INTERACTION * ov * 1e9 / (FP32_PEAK_TFLOPS * 1e12), 2),
         }
+    line["executed"] = executed_flops(args.prec, float(n) * n / (k_ms * 1e-3) / 1e9)
     extras = [] if args.extras == "none" else args.extras.split(",")
+    precs = (args.prec, other)
+    pname = lambda q: "ds_comp" if q == "ds" else "fp32"
     if "batched" in extras:
-        log("[bench] batched clusters")
-        line["batched"] = batched_timing(ctx, args.prec)
+        line["batched"] = {}
+        for q in precs:
+            log(f"[bench] batched clusters ({q})")
+            line["batched"][pname(q)] = batched_timing(ctx, q)
     if "adjoint" in extras:
-        log("[bench] adjoint/forward timing")
-        line["adjoint"] = adjoint_timing(nb, ctx, args.prec)
+        line["adjoint"] = {}
+        for q in precs:
+            log(f"[bench] adjoint/forward timing ({q})")
+            line["adjoint"][pname(q)] = adjoint_timing(nb, ctx, q)
     if "kinds" in extras:
         log("[bench] force-only and nearest-neighbour evaluations")
         line["kinds"] = kinds_timing(ctx, X, V, M, eps, args.prec, k_ms)
@@ -571,8 +610,8 @@ def main():
         log("[bench] one GPU's share of an 8-GPU i-parallel evaluation")
         line["shard8"] = shard_timing(ctx, X, V, M, eps, args.prec, k_ms)
     if "block" in extras:
-        log("[bench] block steps, Salpeter N=65536 to t=1/4")
-        line["block_steps"] = block_run(65536, 0.25, ["ds", "fp32"], ctx=ctx, marks_out=False)
+        log("[bench] block steps, Salpeter N=65536 to t=1 (energy every 1/4)")
+        line["block_steps"] = block_run(65536, 1.0, ["ds", "fp32"], report_every=0.25, ctx=ctx)
     if "shared1k" in extras:
         log("[bench] shared steps, N=1024")
         line["shared1k"] = shared1k_timing(ctx)

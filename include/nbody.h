@@ -165,14 +165,15 @@ int nbody_autotune(nbody_ctx *ctx, hipStream_t stream, nbody_prec prec, double G
  * with r = x_j - x_i, u = v_j - v_i, s = |r|^2 + eps^2.
  * i_self: device int32[n_i] giving, for each i, the j index of that same
  * particle (excluded from the sums) or -1; NULL excludes nothing.  The
- * kernel visits every j, including j = i_self[i]; that pair contributes
- * exactly zero to a and jerk because its rows are bit-identical, and its
- * potential term is removed after the loop (Section 3.1).  The caller must
- * therefore pass, for a self pair, an i row equal to the j row.  With the
- * environment variable NBODY_DEBUG_SELF_CHECK=1 set when the context is
- * created, the call verifies this on the packed rows (and that every
- * i_self < n_j), synchronising the stream, and returns NBODY_ERR_ARG when a
- * row differs.
+ * kernel sweeps every j (Section 3.1 counts all N^2 pairs); in the one or
+ * two j-tiles that hold j = i_self[i] the pair is given zero mass, so it
+ * contributes nothing to a, jerk or pot and the large self potential
+ * m_i/eps never enters a float32 partial sum.  An i_self value outside
+ * [0, n_j) excludes nothing.  With the environment variable
+ * NBODY_DEBUG_SELF_CHECK=1 set when the context is created, the call also
+ * checks that each i row equals the j row i_self names (the same particle)
+ * and that every i_self < n_j, synchronising the stream, and returns
+ * NBODY_ERR_ARG when one does not.
  * I.m is unused.  Returns NBODY_ERR_ARG for NULL rows, n_i < 0, n_j < 0,
  * counts above 2^31 - 1, non-finite G or eps, eps < 0. */
 int nbody_force(nbody_ctx *ctx, hipStream_t stream, nbody_prec prec, double G, double eps,

@@ -168,6 +168,9 @@ static bool valid_tile(const nbody_tile& t) {
 // ranges), and 2^17 i against 2^20 j from 96 to 90 ms (64 ranges).
 constexpr int64_t kLongWG = 32768;
 constexpr int64_t kLongTiles = 64;
+// The long-evaluation split keeps its partial sums (8 rows of 8 bytes per
+// i and range at most) within this many bytes.
+constexpr int64_t kLongPartBytes = (int64_t)1 << 31;
 static int choose_split(int64_t ni, int64_t nj, const nbody_tile& t) {
     int nb, S, jc;
     split_plan(ni, nj, t.wg * t.ipt, t.tile_j, 0, &nb, &S, &jc);
@@ -175,6 +178,7 @@ static int choose_split(int64_t ni, int64_t nj, const nbody_tile& t) {
     const int64_t nbl = (ni + per - 1) / per;
     int64_t Sl = nbl > 0 ? (kLongWG + nbl - 1) / nbl : 1;
     Sl = std::min<int64_t>(Sl, nj / (kLongTiles * t.tile_j));
+    Sl = std::min<int64_t>(Sl, kLongPartBytes / (64 * std::max<int64_t>(ni, 1)));
     return (int)std::max<int64_t>(S, Sl);
 }
 
@@ -315,16 +319,8 @@ static int run_force(nbody_ctx* c, hipStream_t st, int prec, double G, double ep
     if (S > 1) {
         ReduceArgs r{};
         r.ni = (int)ni;
-        r.nj = (int)nj;
         r.S = S;
-        r.prec = prec;
-        r.eps0 = eps0 ? 1 : 0;
         r.part = a.part;
-        r.jpack = jpack;
-        r.iidx = iidx;
-        r.iself = iself;
-        r.self_mode = self_mode;
-        r.eps2 = a.eps2;
         r.G = G;
         for (int q = 0; q < 7; ++q) r.out[q] = a.out[q];
         e = launch_reduce(r, st);
@@ -446,8 +442,21 @@ int nbody_reserve(nbody_ctx* c, int64_t max_i, int64_t max_j) {
     if (int rc = need_device(c)) return rc;
     DeviceGuard g(c->device);
     const size_t ni = (size_t)std::max<int64_t>(max_i, 1), nj = (size_t)std::max<int64_t>(max_j, 1);
+    // split partial sums of the shapes the next calls would take: at max_i
+    // and at every power of two below it (the long-evaluation rule keeps
+    // S x n_i about constant, so the largest is near one of these)
+    size_t part = 0;
+    for (int prec = 0; prec < 2; ++prec)
+        for (int64_t n = (int64_t)ni; n >= 1; n = n == (int64_t)ni ? (int64_t)1 << (63 - __builtin_clzll(n)) : n / 2) {
+            const nbody_tile t = pick_tile(c, prec, n, (int64_t)nj);
+            int nb, S, jc;
+            split_plan(n, (int64_t)nj, t.wg * t.ipt, t.tile_j, t.split, &nb, &S, &jc);
+            if (S > 1) part = std::max(part, sizeof(float2) * 8 * (size_t)S * (size_t)n);
+            if (n == 1) break;
+        }
     int rc = dev_alloc(c, c->ipack, sizeof(float4) * kRecDS * ni);
     if (!rc) rc = dev_alloc(c, c->jpack, sizeof(float4) * kRecDS * nj);
+    if (!rc && part > 0) rc = dev_alloc(c, c->part, part);
     return rc;
 }
 
@@ -906,9 +915,7 @@ static int hermite_step_shared(nbody_hermite* h, hipStream_t st, int64_t t_limit
     if (rc) return rc;
     ReduceArgs r{};
     r.ni = n;
-    r.nj = n;
     r.S = S;
-    r.prec = p;
     r.part = (const float2*)c->part.p;
     r.G = h->o.G;
     r.plan = nullptr;
@@ -970,6 +977,7 @@ static int hermite_enqueue_block(nbody_hermite* h, hipStream_t st) {
     a.eps2 = (float)(h->o.eps * h->o.eps);
     a.G = h->o.G;
     a.self_mode = 1;
+    a.keep_self = 1;   // the i rows are the j records themselves; the potential is not read
     for (int q = 0; q < 7; ++q) a.out[q] = h->f[q];
     a.part = (float2*)c->part.p;
     a.plan = h->plan;
@@ -977,14 +985,7 @@ static int hermite_enqueue_block(nbody_hermite* h, hipStream_t st) {
     if (e != hipSuccess) return hip_err(c, e, "force launch");
     ReduceArgs r{};
     r.ni = n;
-    r.nj = n;
-    r.prec = p;
-    r.eps0 = eps0 ? 1 : 0;
     r.part = a.part;
-    r.jpack = a.jpack;
-    r.iidx = h->idx;
-    r.self_mode = 1;
-    r.eps2 = a.eps2;
     r.G = h->o.G;
     for (int q = 0; q < 7; ++q) r.out[q] = h->f[q];
     r.plan = h->plan;

@@ -12,9 +12,13 @@
 //    wave-uniform (broadcast) LDS load;
 //  * float32 VALU arithmetic with one hardware v_rsq_f32 per pair, no
 //    branch in the loop (the ragged tail is padded with massless records
-//    far away); all N^2 pairs are visited, self included (Section 3.1):
-//    the self pair gives exactly 0 to a and jerk and its potential term is
-//    removed in the epilogue;
+//    far away); all N^2 pairs are visited (Section 3.1).  The self pair is
+//    excluded by index: a tile that holds the own j index of some lane of
+//    the wave (one or two tiles of a self-gravitating sweep) runs a copy of
+//    the loop in which that pair's mass is zeroed, so the large self
+//    potential m_i/eps never enters a float32 partial sum (the paper
+//    subtracts it after the loop; in float32 that leaves the rounding of
+//    every later addition of the tile at the scale of m_i/eps);
 //  * DS_COMP: positions are double-single and the relative coordinate is
 //    (x_j,hi - x_i,hi) + (x_j,lo - x_i,lo); per-tile float32 partial sums
 //    are folded into a two-sum (hi, lo) accumulator;
@@ -29,6 +33,8 @@
 // treecode or leapfrog needs); KIND 2 adds to KIND 0 the nearest neighbour
 // of each i (Section 3.3): one unsoftened r^2 per pair, kept when smaller
 // than the best so far and j is not i itself, so the lowest j wins a tie.
+#include <type_traits>
+
 #include "nbody_internal.h"
 
 namespace nb {
@@ -52,12 +58,17 @@ __device__ __forceinline__ void two_sum_fold(float& hi, float& lo, float p) {
 }
 
 // One work-group's share: i slots ibase + k*WG + tid (k < IPT) below iend,
-// against j in [jb, je).  Results go to the float64 outputs (with the
-// self-potential removal) or to split partial slot `split`.
+// against j in [jb, je).  Results go to the float64 outputs or to split
+// partial slot `split`.
+// LOW (fewer registers, hence more resident waves): the low words of the
+// compensated sums live in LDS (losh, 7 * IPT * WG floats: each lane
+// touches its own words once per tile) and the j tiles are single-buffered
+// (sh[0] only), so no staging registers stay live through the tile loop.
 template <int PREC, int IPT, int TJ, int WG, bool EPS0, bool JS = false, int UNR = 4, bool PIPE = false,
-          int KIND = 0>
+          int KIND = 0, bool LOW = false>
 __device__ __forceinline__ void force_block(const ForceArgs& a, float4 (*sh)[TJ * Rec<PREC>::R], int ibase,
-                                            int iend, int jb, int je, float eps2, int split) {
+                                            int iend, int jb, int je, float eps2, int split,
+                                            float* __restrict__ losh = nullptr) {
     constexpr int R = Rec<PREC>::R;
     constexpr int NE = TJ * R;                  // float4 per tile
     constexpr int NLD = (NE + WG - 1) / WG;     // staging loads per lane
@@ -82,7 +93,11 @@ __device__ __forceinline__ void force_block(const ForceArgs& a, float4 (*sh)[TJ 
         iu[k] = r1.x; iv[k] = r1.y; iw[k] = r1.z;
         lx[k] = r2.x; ly[k] = r2.y; lz[k] = r2.z;
     }
-    // nearest-neighbour state (KIND 2): best r^2, its j, and the j index of i
+    // the j index of each i (-1: none) and the nearest-neighbour state
+    // (KIND 2): best r^2 and its j.  With eps = 0 the self pair has s = 0
+    // and drops out through the s > 0 select, so only the neighbour search
+    // needs the index there.
+    constexpr bool kSelf = !EPS0 || KIND == 2;
     float bnr[IPT];
     int bnj[IPT], selfk[IPT];
 #pragma unroll
@@ -90,15 +105,33 @@ __device__ __forceinline__ void force_block(const ForceArgs& a, float4 (*sh)[TJ 
         const int ii = ibase + k * WG + tid;
         bnr[k] = __builtin_inff();
         bnj[k] = -1;
-        selfk[k] = (KIND == 2 && ii < iend) ? self_index(a.self_mode, a.iidx, a.iself, ii) : -1;
+        selfk[k] = (kSelf && ii < iend) ? self_index(a.self_mode, a.iidx, a.iself, ii) : -1;
     }
+    // Does the j range [j0, j0 + len) hold the own index of any lane of
+    // this wave?  (One compare per i-slot per tile; the answer is uniform
+    // over the wave, so the branch it drives does not diverge.)
+    auto wave_has_self = [&](int j0, int len) {
+        if (EPS0 || a.keep_self) return false;
+        bool f = false;
+#pragma unroll
+        for (int k = 0; k < IPT; ++k) f |= (unsigned)(selfk[k] - j0) < (unsigned)len;
+        return __ballot(f) != 0;
+    };
 
+    constexpr bool LO_LDS = LOW && PREC == 1;
     float acc[IPT][7];
-    float chi[IPT][7], clo[IPT][7];
+    float chi[IPT][7], clo[LO_LDS ? 1 : IPT][7];
 #pragma unroll
     for (int k = 0; k < IPT; ++k)
 #pragma unroll
-        for (int q = 0; q < 7; ++q) { acc[k][q] = 0.f; chi[k][q] = 0.f; clo[k][q] = 0.f; }
+        for (int q = 0; q < 7; ++q) {
+            acc[k][q] = 0.f;
+            chi[k][q] = 0.f;
+            if (LO_LDS)
+                losh[(k * 7 + q) * WG + tid] = 0.f;
+            else
+                clo[k][q] = 0.f;
+        }
 
     float4 stg[NLD];
     auto load_tile = [&](int t) {
@@ -129,9 +162,13 @@ __device__ __forceinline__ void force_block(const ForceArgs& a, float4 (*sh)[TJ 
     // the instruction that reads it
     float eps2v;
     asm volatile("v_mov_b32 %0, %1" : "=v"(eps2v) : "s"(eps2));
-    auto interact = [&](const float4& q0, const float4& q1, const float4& q2, int jidx) {
+    // MASK (a std::integral_constant): the self pair j == selfk[k] gets zero
+    // mass, so it contributes exactly nothing to any sum.
+    auto interact = [&](auto maskc, const float4& q0, const float4& q1, const float4& q2, int jidx) {
+        constexpr bool MASK = decltype(maskc)::value;
 #pragma unroll
         for (int k = 0; k < IPT; ++k) {
+            const float mj = (MASK && !EPS0 && jidx == selfk[k]) ? 0.f : q0.w;
             float dx, dy, dz;
             if (PREC == 1) {
                 dx = (q0.x - ix[k]) + (q2.x - lx[k]);
@@ -155,7 +192,7 @@ __device__ __forceinline__ void force_block(const ForceArgs& a, float4 (*sh)[TJ 
             float rinv = __builtin_amdgcn_rsqf(s);
             if (EPS0) rinv = s > 0.f ? rinv : 0.f;
             if (KIND == 1) {
-                const float mr = q0.w * rinv;
+                const float mr = mj * rinv;
                 const float mr3 = mr * (rinv * rinv);
                 acc[k][0] = fmaf(mr3, dx, acc[k][0]);
                 acc[k][1] = fmaf(mr3, dy, acc[k][1]);
@@ -166,7 +203,7 @@ __device__ __forceinline__ void force_block(const ForceArgs& a, float4 (*sh)[TJ 
             const float ux = q1.x - iu[k], uy = q1.y - iv[k], uz = q1.z - iw[k];
             const float rv = fmaf(dz, uz, fmaf(dy, uy, dx * ux));
             const float rinv2 = rinv * rinv;
-            const float mr = q0.w * rinv;
+            const float mr = mj * rinv;
             const float mr3 = mr * rinv2;
             const float al = 3.0f * rv * rinv2;
             acc[k][0] = fmaf(mr3, dx, acc[k][0]);
@@ -184,41 +221,59 @@ __device__ __forceinline__ void force_block(const ForceArgs& a, float4 (*sh)[TJ 
             for (int k = 0; k < IPT; ++k)
 #pragma unroll
                 for (int q = 0; q < 7; ++q) {
-                    two_sum_fold(chi[k][q], clo[k][q], acc[k][q]);
+                    if (LO_LDS) {
+                        float lo = losh[(k * 7 + q) * WG + tid];
+                        two_sum_fold(chi[k][q], lo, acc[k][q]);
+                        losh[(k * 7 + q) * WG + tid] = lo;
+                    } else {
+                        two_sum_fold(chi[k][q], clo[k][q], acc[k][q]);
+                    }
                     acc[k][q] = 0.f;
                 }
         }
     };
 
+    const std::integral_constant<bool, false> plain{};
+    const std::integral_constant<bool, true> masked{};
     if (JS) {
         // j records read by wave-uniform loads (scalar data cache); chunks of
         // TJ j between compensated folds; no LDS, no barrier
         const float4* __restrict__ jp = a.jpack;
-        for (int j0 = jb; j0 < je; j0 += TJ) {
-            const int j1 = min(je, j0 + TJ);
-#pragma unroll UNR
+        auto chunk = [&](auto maskc, int j0, int j1) {
+            constexpr int U = decltype(maskc)::value ? 1 : UNR;
+#pragma unroll U
             for (int j = j0; j < j1; ++j) {
                 const float4 q0 = jp[(size_t)j * R + 0];
                 const float4 q1 = jp[(size_t)j * R + 1];
                 float4 q2 = make_float4(0.f, 0.f, 0.f, 0.f);
                 if (PREC == 1) q2 = jp[(size_t)j * R + 2];
-                interact(q0, q1, q2, j);
+                interact(maskc, q0, q1, q2, j);
             }
+        };
+        for (int j0 = jb; j0 < je; j0 += TJ) {
+            const int j1 = min(je, j0 + TJ);
+            if (wave_has_self(j0, j1 - j0))
+                chunk(masked, j0, j1);
+            else
+                chunk(plain, j0, j1);
             fold();
         }
     } else {
-        if (ntiles > 0) {
-            load_tile(0);
-            store_tile(0);
-        }
-        __syncthreads();
-
-        for (int t = 0; t < ntiles; ++t) {
-            const int buf = t & 1;
-            if (t + 1 < ntiles) load_tile(t + 1);
-            const float4* tile = sh[buf];
-            const int jt = jb + t * TJ;
-            if (PIPE) {
+        // one tile from LDS; jt is the j index of its first record.  The
+        // masked copy (rare: the tiles that hold a lane's own index) is a
+        // plain loop, so that it never sets the kernel's register count.
+        auto sweep = [&](auto maskc, const float4* tile, int jt) {
+            constexpr bool MASK = decltype(maskc)::value;
+            if (MASK) {
+#pragma unroll 1
+                for (int jj = 0; jj < TJ; ++jj) {
+                    const float4 q0 = tile[jj * R + 0];
+                    const float4 q1 = tile[jj * R + 1];
+                    float4 q2 = make_float4(0.f, 0.f, 0.f, 0.f);
+                    if (PREC == 1) q2 = tile[jj * R + 2];
+                    interact(maskc, q0, q1, q2, jt + jj);
+                }
+            } else if (PIPE) {
                 // software pipeline: the record of j+1 is read from LDS while
                 // j is being computed
                 float4 q0 = tile[0], q1 = tile[1];
@@ -231,7 +286,7 @@ __device__ __forceinline__ void force_block(const ForceArgs& a, float4 (*sh)[TJ 
                     const float4 n1 = tile[jn * R + 1];
                     float4 n2 = make_float4(0.f, 0.f, 0.f, 0.f);
                     if (PREC == 1) n2 = tile[jn * R + 2];
-                    interact(q0, q1, q2, jt + jj);
+                    interact(maskc, q0, q1, q2, jt + jj);
                     q0 = n0;
                     q1 = n1;
                     q2 = n2;
@@ -243,12 +298,43 @@ __device__ __forceinline__ void force_block(const ForceArgs& a, float4 (*sh)[TJ 
                     const float4 q1 = tile[jj * R + 1];
                     float4 q2 = make_float4(0.f, 0.f, 0.f, 0.f);
                     if (PREC == 1) q2 = tile[jj * R + 2];
-                    interact(q0, q1, q2, jt + jj);
+                    interact(maskc, q0, q1, q2, jt + jj);
                 }
             }
-            fold();
-            if (t + 1 < ntiles) store_tile(buf ^ 1);
+        };
+        if (LOW) {
+            // single buffer: stage, barrier, sweep, barrier
+            for (int t = 0; t < ntiles; ++t) {
+                load_tile(t);
+                store_tile(0);
+                __syncthreads();
+                const int jt = jb + t * TJ;
+                if (wave_has_self(jt, TJ))
+                    sweep(masked, sh[0], jt);
+                else
+                    sweep(plain, sh[0], jt);
+                fold();
+                __syncthreads();
+            }
+        } else {
+            if (ntiles > 0) {
+                load_tile(0);
+                store_tile(0);
+            }
             __syncthreads();
+
+            for (int t = 0; t < ntiles; ++t) {
+                const int buf = t & 1;
+                if (t + 1 < ntiles) load_tile(t + 1);
+                const int jt = jb + t * TJ;
+                if (wave_has_self(jt, TJ))
+                    sweep(masked, sh[buf], jt);
+                else
+                    sweep(plain, sh[buf], jt);
+                fold();
+                if (t + 1 < ntiles) store_tile(buf ^ 1);
+                __syncthreads();
+            }
         }
     }
 
@@ -261,7 +347,7 @@ __device__ __forceinline__ void force_block(const ForceArgs& a, float4 (*sh)[TJ 
 #pragma unroll
         for (int q = 0; q < 7; ++q) {
             hi[q] = PREC == 1 ? chi[k][q] : acc[k][q];
-            lo[q] = PREC == 1 ? clo[k][q] : 0.f;
+            lo[q] = PREC != 1 ? 0.f : LO_LDS ? losh[(k * 7 + q) * WG + tid] : clo[LO_LDS ? 0 : k][q];
         }
         int nnj = bnj[k];
         float nnr = bnr[k];
@@ -276,15 +362,7 @@ __device__ __forceinline__ void force_block(const ForceArgs& a, float4 (*sh)[TJ 
                 if (KIND != 1 || q < 3 || q == 6) a.part[base + (size_t)q * a.ni] = make_float2(hi[q], lo[q]);
             if (KIND == 2) a.nnpart[(size_t)split * a.ni + ii] = make_float2(nnr, __int_as_float(nnj));
         } else {
-            double pot = (double)hi[6] + (double)lo[6];
-            if (!EPS0) {
-                const int self = self_index(a.self_mode, a.iidx, a.iself, ii);
-                if (self >= 0 && self < a.nj) {
-                    // remove exactly the float32 term the loop added for j = i
-                    const float ms = a.jpack[(size_t)self * R].w;
-                    pot -= (double)(ms * __builtin_amdgcn_rsqf(eps2));
-                }
-            }
+            const double pot = (double)hi[6] + (double)lo[6];
 #pragma unroll
             for (int q = 0; q < 6; ++q)
                 if (KIND != 1 || q < 3) a.out[q][ii] = a.G * ((double)hi[q] + (double)lo[q]);
@@ -297,16 +375,24 @@ __device__ __forceinline__ void force_block(const ForceArgs& a, float4 (*sh)[TJ 
     }
 }
 
-// WPE > 0 asks the compiler for at least WPE waves per SIMD (a register cap);
-// UNR >= 100 selects the software-pipelined LDS loop with unroll UNR - 100.
+// WPE > 0 asks the compiler for at least WPE waves per SIMD (a register cap).
+// UNR encodes the loop form: d (< 100) unroll d; 100 + d the
+// software-pipelined LDS loop; 200 + d the low-register form (LOW above);
+// 300 + d both.
+constexpr int unr_depth(int u) { return u % 100; }
+constexpr bool unr_pipe(int u) { return (u / 100) % 2 == 1; }
+constexpr bool unr_low(int u) { return u >= 200; }
+
 template <int PREC, int IPT, int TJ, int WG, bool EPS0, int UNR, int WPE>
 __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(WPE > 0 ? WPE : 1)))
 void force_kernel(ForceArgs a) {
-    __shared__ float4 sh[2][TJ * Rec<PREC>::R];
+    constexpr bool LOW = unr_low(UNR);
+    __shared__ float4 sh[LOW ? 1 : 2][TJ * Rec<PREC>::R];
+    __shared__ float losh[LOW && PREC == 1 ? 7 * IPT * WG : 1];
     const int jb = blockIdx.y * a.jchunk;
     const int je = min(a.nj, jb + a.jchunk);
-    force_block<PREC, IPT, TJ, WG, EPS0, false, (UNR >= 100 ? UNR - 100 : UNR), (UNR >= 100)>(
-        a, sh, blockIdx.x * (WG * IPT), a.ni, jb, je, a.eps2, blockIdx.y);
+    force_block<PREC, IPT, TJ, WG, EPS0, false, unr_depth(UNR), unr_pipe(UNR), 0, LOW>(
+        a, sh, blockIdx.x * (WG * IPT), a.ni, jb, je, a.eps2, blockIdx.y, losh);
 }
 
 // The force-only (KIND 1) and nearest-neighbour (KIND 2) evaluations.
@@ -315,7 +401,7 @@ __global__ __launch_bounds__(WG) void force_kernel_kind(ForceArgs a) {
     __shared__ float4 sh[2][TJ * Rec<PREC>::R];
     const int jb = blockIdx.y * a.jchunk;
     const int je = min(a.nj, jb + a.jchunk);
-    force_block<PREC, IPT, TJ, WG, EPS0, false, (UNR >= 100 ? UNR - 100 : UNR), (UNR >= 100), KIND>(
+    force_block<PREC, IPT, TJ, WG, EPS0, false, unr_depth(UNR), unr_pipe(UNR), KIND>(
         a, sh, blockIdx.x * (WG * IPT), a.ni, jb, je, a.eps2, blockIdx.y);
 }
 
@@ -338,7 +424,7 @@ __global__ __launch_bounds__(WG) void force_kernel_plan(ForceArgs a) {
         const int ib = v % nb, s = v / nb;
         const int jb = s * b.jchunk;
         const int je = min(b.nj, jb + b.jchunk);
-        force_block<PREC, IPT, TJ, WG, EPS0, false, (UNR >= 100 ? UNR - 100 : UNR), (UNR >= 100)>(
+        force_block<PREC, IPT, TJ, WG, EPS0, false, unr_depth(UNR), unr_pipe(UNR)>(
             b, sh, ib * (WG * IPT), n, jb, je, b.eps2, s);
     }
 }
@@ -379,20 +465,12 @@ __global__ __launch_bounds__(WG) void force_batched_kernel(ForceArgs a, BatchArg
     }
 }
 
-// Float64 reduction of split partials in a fixed order, then the
-// self-potential removal and the factor G.  Few ranges: one thread per
+// Float64 reduction of split partials in a fixed order, then the factor G
+// (the self pair never entered a partial).  Few ranges: one thread per
 // (quantity, i) sums s = 0 .. S-1 in order.  Many ranges: one wave per
 // (quantity, i); lane l sums s = l, l + 64, ... in order, then a fixed
 // butterfly over the 64 lane sums.  Either way the result depends only on S.
-__device__ __forceinline__ double reduce_finish(const ReduceArgs& a, int q, int i, double s) {
-    if (q == 6 && !a.eps0) {
-        const int self = self_index(a.self_mode, a.iidx, a.iself, i);
-        if (self >= 0 && self < a.nj) {
-            const int R = a.prec == 0 ? kRecFP32 : kRecDS;
-            const float ms = a.jpack[(size_t)self * R].w;
-            s -= (double)(ms * __builtin_amdgcn_rsqf(a.eps2));
-        }
-    }
+__device__ __forceinline__ double reduce_finish(const ReduceArgs& a, int q, double s) {
     return q < 6 ? a.G * s : -a.G * s;
 }
 
@@ -408,7 +486,7 @@ __global__ __launch_bounds__(256) void reduce_kernel(ReduceArgs a) {
         s += (double)p.x;
         s += (double)p.y;
     }
-    a.out[q][i] = reduce_finish(a, q, i, s);
+    a.out[q][i] = reduce_finish(a, q, s);
 }
 
 __global__ __launch_bounds__(256) void reduce_wave_kernel(ReduceArgs a) {
@@ -425,7 +503,7 @@ __global__ __launch_bounds__(256) void reduce_wave_kernel(ReduceArgs a) {
         s += (double)p.y;
     }
     for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
-    if (lane == 0) a.out[q][i] = reduce_finish(a, q, i, s);
+    if (lane == 0) a.out[q][i] = reduce_finish(a, q, s);
 }
 
 // Nearest neighbour over the j-ranges: the smallest r^2, the lower range
@@ -590,6 +668,10 @@ static const Variant kVariants[] = {
     NB_X(0, 1, 256, 256, 102, 0), NB_X(0, 1, 256, 256, 104, 0), NB_X(0, 2, 256, 256, 101, 0),
     NB_X(1, 1, 256, 256, 102, 0), NB_X(1, 1, 256, 256, 104, 0), NB_X(1, 2, 256, 256, 101, 0),
     NB_X(1, 1, 128, 256, 102, 0), NB_X(1, 1, 256, 128, 102, 0),
+    // low-register forms (lo words in LDS, single-buffered tiles; 200 + d,
+    // pipelined 300 + d)
+    NB_X(1, 2, 256, 256, 202, 0), NB_X(1, 2, 256, 256, 301, 0), NB_X(1, 2, 128, 256, 202, 0),
+    NB_X(1, 2, 128, 256, 301, 0), NB_X(0, 2, 256, 256, 202, 0), NB_X(0, 1, 256, 256, 302, 0),
     // short tiles for small, latency-bound sets (more j-ranges, shorter sweeps)
     NB_X(0, 1, 16, 64, 4, 0), NB_X(0, 1, 32, 64, 4, 0), NB_X(0, 1, 16, 128, 4, 0), NB_X(0, 1, 32, 128, 4, 0),
     NB_X(1, 1, 16, 64, 4, 0), NB_X(1, 1, 32, 64, 4, 0), NB_X(1, 1, 16, 128, 4, 0), NB_X(1, 1, 32, 128, 4, 0),

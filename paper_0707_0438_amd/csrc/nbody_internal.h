@@ -97,6 +97,8 @@ struct ForceArgs {
     double G;
     const int32_t* iself;   // self j index per i (used when self_mode == 0; NULL: none)
     int self_mode;          // 0: iself[i], 1: iidx[i], 2: i itself
+    int keep_self;          // 1: the self pair is not masked (its i row is a copy of its j
+                            //    row, so a and jerk get exactly 0; the potential row is unused)
     double* out[7];         // ax ay az jx jy jz pot (final mode)
     float2* part;           // [S][7][ni] (hi, lo) partials (partial mode)
     const DevPlan* plan;    // plan-driven launch: ni, S, jchunk come from here
@@ -106,13 +108,8 @@ struct ForceArgs {
 };
 
 struct ReduceArgs {
-    int ni, nj, S, prec, eps0;
+    int ni, S;
     const float2* part;
-    const float4* jpack;
-    const int32_t* iidx;
-    const int32_t* iself;
-    int self_mode;
-    float eps2;
     double G;
     double* out[7];
     const DevPlan* plan;    // plan-driven launch: ni and S come from here
@@ -351,7 +348,7 @@ __host__ __device__ inline int64_t block_level(double crit, int64_t dt_old, int6
     const int64_t dmax = (int64_t)1 << (lmax + 20);
     int64_t q = dmin;
     // crit must be a positive finite number; otherwise the smallest level.
-    if (crit > 0.0 && crit <= 1.0e300) {
+    if (crit > 0.0 && isfinite(crit)) {
         // largest power of two (in ticks) not above crit, within [dmin, dmax]
         const double c_ticks = crit * 1048576.0;
         while (q < dmax && (double)(q << 1) <= c_ticks) q <<= 1;

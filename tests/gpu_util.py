@@ -49,6 +49,50 @@ def scaled_err_stats(got, ref):
     return {"p50": float(rank(0.5)), "p99": float(rank(0.99)), "max": float(e[-1])}
 
 
+def mass_grad_scale(xi, vi, xj, vj, eps, ga, gj=None, gp=None, iself=None, G=1.0, chunk=256):
+    """Per-element scale of dL/dm_j for L = sum_i ga_i.a_i + gj_i.jerk_i +
+    gp_i pot_i: sum over i of the absolute value of each pair's term
+    G [s^-3/2 ga_i.r + gj_i.(s^-3/2 u - 3 s^-5/2 (r.u) r) - gp_i s^-1/2]
+    (r = x_j - x_i, u = v_j - v_i, s = r.r + eps^2; self pairs by index and
+    pairs at s = 0 left out).  The gradient itself is the signed sum of
+    these terms, so |error| / scale is the error relative to the size of the
+    arithmetic that produced it, which a cancelling sum does not hide."""
+    xi, vi, xj, vj = (np.asarray(a, dtype=np.float64) for a in (xi, vi, xj, vj))
+    ni, nj = xi.shape[1], xj.shape[1]
+    gj = np.zeros((3, ni)) if gj is None else np.asarray(gj, dtype=np.float64)
+    gp = np.zeros(ni) if gp is None else np.asarray(gp, dtype=np.float64)
+    out = np.zeros(nj)
+    for a in range(0, ni, chunk):
+        b = min(ni, a + chunk)
+        r = xj[:, None, :] - xi[:, a:b, None]          # (3, ci, nj)
+        u = vj[:, None, :] - vi[:, a:b, None]
+        s = (r * r).sum(0) + eps * eps
+        ok = s > 0
+        if iself is not None:
+            ii = np.asarray(iself)[a:b]
+            ok &= ii[:, None] != np.arange(nj)[None, :]
+        A = np.where(ok, 1.0 / np.sqrt(np.where(ok, s, 1.0)), 0.0)
+        B, C = A ** 3, A ** 5
+        ru = (r * u).sum(0)
+        t = B * (ga[:, a:b, None] * r).sum(0)
+        t += (gj[:, a:b, None] * (B * u - 3.0 * C * ru * r)).sum(0)
+        t -= gp[a:b, None] * A
+        out += np.abs(G * t).sum(0)
+    return out
+
+
+def elem_err_stats(got, ref, scale):
+    """|got - ref| / scale per element, nearest-rank percentiles."""
+    got = np.asarray(got, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    e = np.sort(np.abs(got - ref) / np.where(scale > 0, scale, 1.0))
+    n = e.size
+    if n == 0:
+        return {"p50": 0.0, "p99": 0.0, "max": 0.0}
+    rank = lambda q: e[max(0, int(np.ceil(q * n)) - 1)]
+    return {"p50": float(rank(0.5)), "p99": float(rank(0.99)), "max": float(e[-1])}
+
+
 # Accuracy bars (per-particle relative error, nearest-rank p99) against the
 # float64 oracle.  DS_COMP: the acceleration bar is the stated target
 # (1e-5); jerk and potential bars are the readings taken for them.  Plain

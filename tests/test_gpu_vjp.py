@@ -5,7 +5,7 @@ import pytest
 
 import nbody_inputs as ics
 import oracle
-from gpu_util import dev, host, rel_err_stats, scaled_err_stats
+from gpu_util import dev, elem_err_stats, host, mass_grad_scale, rel_err_stats
 
 pytestmark = pytest.mark.gpu
 
@@ -26,12 +26,13 @@ def cotangents(n, seed):
     return g.normal(size=(3, n)), g.normal(size=(3, n)), g.normal(size=n)
 
 
-def report(label, prec, pairs):
+def report(label, prec, pairs, mscale=None):
     """Vector gradients: per-particle relative error of the 3-vector; scalar
-    (mass) gradients: error over the rms of the reference."""
+    (mass) gradients: error over the per-element scale sum_i |pair term|
+    (``mscale``, see gpu_util.mass_grad_scale)."""
     out = {}
     for name, got, ref in pairs:
-        st = rel_err_stats(got, ref) if np.ndim(ref) == 2 else scaled_err_stats(got, ref)
+        st = rel_err_stats(got, ref) if np.ndim(ref) == 2 else elem_err_stats(got, ref, mscale)
         out[name] = st
     print(label, prec, {k: f"p99={v['p99']:.2e} max={v['max']:.2e}" for k, v in out.items()}, flush=True)
     return out
@@ -46,8 +47,9 @@ def test_vjp_self_against_oracle(ctx, prec):
                                                iself=np.arange(p.n))
     gx, gv, gm = ctx.force_vjp_self(dev(p.pos), dev(p.vel), dev(p.mass), eps, dev(ga), dev(gj),
                                     dev(gp), prec=prec)
+    sc = mass_grad_scale(p.pos, p.vel, p.pos, p.vel, eps, ga, gj, gp, iself=np.arange(p.n))
     st = report("vjp_self n=1500", prec, [("gx", host(gx), gxi + gxj), ("gv", host(gv), gvi + gvj),
-                                          ("gm", host(gm), gmj)])
+                                          ("gm", host(gm), gmj)], sc)
     for k in st:
         assert st[k]["p99"] <= VJP_BARS[prec], (k, st[k])
 
@@ -63,7 +65,9 @@ def test_vjp_general_subset_and_disjoint(ctx, prec):
     got = ctx.force_vjp(dev(p.pos[:, sel]), dev(p.vel[:, sel]), dev(p.pos), dev(p.vel), dev(p.mass), eps,
                         dev(ga), dev(gj), dev(gp), prec=prec, i_self=dev(sel.astype(np.int32)))
     torch.cuda.synchronize()
-    st = report("vjp subset", prec, [(k, host(got[k]), r) for k, r in zip(("xi", "vi", "xj", "vj", "mj"), ref)])
+    sc = mass_grad_scale(p.pos[:, sel], p.vel[:, sel], p.pos, p.vel, eps, ga, gj, gp, iself=sel)
+    st = report("vjp subset", prec, [(k, host(got[k]), r) for k, r in zip(("xi", "vi", "xj", "vj", "mj"), ref)],
+                sc)
     for k in st:
         assert st[k]["p99"] <= VJP_BARS[prec], (k, st[k])
     # disjoint sets, no jerk / potential cotangents
@@ -71,7 +75,9 @@ def test_vjp_general_subset_and_disjoint(ctx, prec):
     ga2 = np.random.default_rng(5).normal(size=(3, q.n))
     ref = oracle.force_vjp(q.pos, q.vel, p.pos, p.vel, p.mass, eps, ga2)
     got = ctx.force_vjp(dev(q.pos), dev(q.vel), dev(p.pos), dev(p.vel), dev(p.mass), eps, dev(ga2), prec=prec)
-    st = report("vjp disjoint", prec, [(k, host(got[k]), r) for k, r in zip(("xi", "vi", "xj", "vj", "mj"), ref)])
+    sc = mass_grad_scale(q.pos, q.vel, p.pos, p.vel, eps, ga2)
+    st = report("vjp disjoint", prec, [(k, host(got[k]), r) for k, r in zip(("xi", "vi", "xj", "vj", "mj"), ref)],
+                sc)
     for k in ("xi", "xj", "mj"):
         assert st[k]["p99"] <= VJP_BARS[prec], (k, st[k])
     # ga only: velocities do not enter a, so their cotangents vanish exactly
@@ -87,9 +93,10 @@ def test_vjp_fused_equals_two_pass(ctx):
     two = ctx.force_vjp(X, V, X, V, M, 0.02, dev(ga), dev(gj), dev(gp),
                         i_self=torch.arange(p.n, dtype=torch.int32, device="cuda"))
     torch.cuda.synchronize()
+    sc = mass_grad_scale(p.pos, p.vel, p.pos, p.vel, 0.02, ga, gj, gp, iself=np.arange(p.n))
     st = report("fused vs two-pass", "ds", [("gx", host(gx), host(two["xi"] + two["xj"])),
                                             ("gv", host(gv), host(two["vi"] + two["vj"])),
-                                            ("gm", host(gm), host(two["mj"]))])
+                                            ("gm", host(gm), host(two["mj"]))], sc)
     for k in st:
         assert st[k]["p99"] <= 1e-5
 
