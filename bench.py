@@ -251,7 +251,7 @@ def adjoint_timing(nb, ctx, prec, reps=10):
             "backward_over_forward": round(t_adj / t_run, 3)}
 
 
-def batched_timing(ctx, prec, steps=32):
+def batched_timing(ctx, prec, steps=32, graph=True):
     """512 independent Plummer clusters (N_c log-uniform in [64, 8192],
     eps_c = 1/(4 N_c^(1/3))), 32 shared Hermite steps of 1/256: one captured
     hipGraph against the same steps launched eagerly and against one
@@ -282,7 +282,7 @@ def batched_timing(ctx, prec, steps=32):
         torch.cuda.synchronize()
         return time.perf_counter() - t0
 
-    t_graph = run("graph")
+    t_graph = run("graph") if graph else float("nan")
     t_eager = run("eager")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -297,9 +297,10 @@ def batched_timing(ctx, prec, steps=32):
                         f"(total {n} particles, sum N_c^2 = {inter_step:.4g}), eps_c = 1/(4 N_c^(1/3)); "
                         "32 shared Hermite steps of 1/256",
             "tile": tile, "autotuned_force_ms": round(tile_ms, 3),
-            "graph_ms": round(t_graph * 1e3, 2), "eager_ms": round(t_eager * 1e3, 2),
+            "graph_ms": round(t_graph * 1e3, 2) if graph else None, "eager_ms": round(t_eager * 1e3, 2),
             "per_cluster_ms": round(t_per * 1e3, 2),
-            "graph_Gint_s": round(tot / t_graph / 1e9, 1), "eager_Gint_s": round(tot / t_eager / 1e9, 1),
+            "graph_Gint_s": round(tot / t_graph / 1e9, 1) if graph else None,
+            "eager_Gint_s": round(tot / t_eager / 1e9, 1),
             "per_cluster_Gint_s": round(tot / t_per / 1e9, 1)}
 
 
@@ -495,6 +496,9 @@ def main():
     ap.add_argument("--extras", default="batched,adjoint,kinds,shard,block,shared1k",
                     help="comma list of extra measurements (batched, adjoint, kinds, shard, block, shared1k) or 'none'")
     ap.add_argument("--report-every", type=float, default=0.0)
+    ap.add_argument("--no-graph", action="store_true",
+                    help="launch the batched steps eagerly only (no hipGraph capture), e.g. under "
+                         "profiler counter passes")
     args = ap.parse_args()
     if args.copy_calibration:
         copy_calibration()
@@ -597,7 +601,7 @@ def main():
         line["batched"] = {}
         for q in precs:
             log(f"[bench] batched clusters ({q})")
-            line["batched"][pname(q)] = batched_timing(ctx, q)
+            line["batched"][pname(q)] = batched_timing(ctx, q, graph=not args.no_graph)
     if "adjoint" in extras:
         line["adjoint"] = {}
         for q in precs:

@@ -72,6 +72,8 @@ struct nbody_hermite {
     float4* spack = nullptr;  // shared steps: records of all particles predicted to spack_tn
     int64_t spack_tn = -1;    // tick those records are valid for (-1: none)
     int64_t* gmin2 = nullptr; // block steps: two arrays of chunk minima of t + dt (this step's, next)
+    uint64_t* gpub = nullptr; // block steps: per-chunk published counts of the fused front end
+    uint32_t front_tag = 0;   // tag of the last enqueued block step (never 0 once used)
     int gpar = 0;             // which of the two holds this step's
     bool gmin_ok = false;     // false: recompute this step's before use
     int64_t t_ticks = 0;
@@ -723,7 +725,8 @@ int nbody_hermite_create(nbody_ctx* c, nbody_hermite** hp, int64_t n, const nbod
                          r256(sizeof(int32_t) * nn) + r256(sizeof(int64_t) * 2) + r256(sizeof(int64_t)) +
                          r256(sizeof(double) * 2) + r256(sizeof(DevPlan)) +
                          (o->shared_dt_log2 != 0 ? r256(sizeof(float4) * kRecDS * nn) : 0) +
-                         r256(sizeof(int64_t) * blk_scratch_words((int)n));
+                         r256(sizeof(int64_t) * blk_scratch_words((int)n)) +
+                         r256(sizeof(uint64_t) * blk_scratch_words((int)n) / 2);
     ++c->alloc_count;
     if (c->fail_alloc_at > 0 && c->alloc_count == c->fail_alloc_at) {
         delete h;
@@ -753,6 +756,15 @@ int nbody_hermite_create(nbody_ctx* c, nbody_hermite** hp, int64_t n, const nbod
     h->plan = (DevPlan*)take(sizeof(DevPlan));
     if (o->shared_dt_log2 != 0) h->spack = (float4*)take(sizeof(float4) * kRecDS * nn);   // shared steps only
     h->gmin2 = (int64_t*)take(sizeof(int64_t) * blk_scratch_words((int)n));
+    h->gpub = (uint64_t*)take(sizeof(uint64_t) * blk_scratch_words((int)n) / 2);
+    // the published counts start untagged (tag 0 is never used)
+    e = launch_fill_i64((int64_t*)h->gpub, blk_scratch_words((int)n) / 2, 0, nullptr);
+    if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
+    if (e != hipSuccess) {
+        (void)hipFree(h->block);
+        delete h;
+        return hip_err(c, e, "hermite scratch clear");
+    }
     *hp = h;
     return NBODY_OK;
 }
@@ -964,8 +976,14 @@ static int hermite_enqueue_block(nbody_hermite* h, hipStream_t st) {
     const bool need_min = !h->gmin_ok;
     h->gmin_ok = false;   // until every launch of this step is in
     const bool eps0 = h->o.eps == 0.0;
+#if NB_BLK_FRONT_FUSED
+    if (++h->front_tag == 0) h->front_tag = 1;
+    hipError_t e = launch_blk_front_fused(pa, h->dt, h->idx, h->sel2, h->plan, h->gpub, h->front_tag, gmin,
+                                          gmin_next, need_min, !eps0, st);
+#else
     hipError_t e = launch_blk_front(pa, h->dt, h->idx, h->sel2, h->plan, (int64_t*)c->sel.p + 2, gmin, gmin_next,
                                     need_min, !eps0, st);
+#endif
     if (e != hipSuccess) return hip_err(c, e, "select/pack/plan launch");
     ForceArgs a{};
     a.ipack = (const float4*)c->jpack.p;
@@ -1034,6 +1052,9 @@ static int hermite_block_run(nbody_hermite* h, hipStream_t st, int64_t t_limit, 
         DevPlan p;
         rc = plan_read(h, st, &p);
         if (rc) return rc;
+        if (p.frozen == 2)
+            return set_err(h->ctx, NBODY_ERR_DEVICE,
+                           "block step: a wait for the chunk counts of the front end did not end");
         if (last_nact) *last_nact = p.frozen ? 0 : p.n_act;
         if (p.frozen || (max_steps > 0 && done >= max_steps)) break;
         chunk = std::min(chunk * 2, 64);

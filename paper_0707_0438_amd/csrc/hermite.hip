@@ -247,6 +247,26 @@ __global__ __launch_bounds__(kSelWG) void blk_min_kernel(int n, int ch, const in
     if (threadIdx.x == 0) gmin[blockIdx.x] = m;
 }
 
+constexpr int kFrontSpin = 1 << 20;
+
+__device__ __forceinline__ void blk_plan_write(DevPlan* plan, int64_t total, int64_t tn, int n, int big_ok) {
+    const int big = big_ok && kBlkBigMin > 0 && total >= kBlkBigMin;
+    int nb, S, jc;
+    if (big)
+        split_plan(total, n, kBlkBigWG, kBlkBigTile, 0, &nb, &S, &jc, 1);
+    else
+        split_plan(total, n, kBlkSmallWG, kBlkSmallTile, 0, &nb, &S, &jc, total <= kBlkTinyMax ? 1 : kBlkMinTiles);
+    plan->shape = big;
+    plan->n_act = total;
+    plan->t_next = tn;
+    plan->nb = nb;
+    plan->S = S;
+    plan->jchunk = jc;
+    plan->steps += 1;
+    plan->sum_active += total;
+    plan->t_last = tn;
+}
+
 // gmin holds this step's chunk minima.  gmin_next receives, per chunk, the
 // minimum of t + dt over the particles that are not due (the corrector then
 // lowers it with the new t + dt of the due ones), so the next step needs no
@@ -330,24 +350,134 @@ __global__ __launch_bounds__(kSelWG) void blk_write_plan_kernel(int n, int ch, i
             plan->frozen = 1;
         } else {
             // large blocks take the large direct evaluations' shape
-            const int big = big_ok && kBlkBigMin > 0 && total >= kBlkBigMin;
-            int nb, S, jc;
-            if (big)
-                split_plan(total, n, kBlkBigWG, kBlkBigTile, 0, &nb, &S, &jc, 1);
-            else
-                split_plan(total, n, kBlkSmallWG, kBlkSmallTile, 0, &nb, &S, &jc,
-                           total <= kBlkTinyMax ? 1 : kBlkMinTiles);
-            plan->shape = big;
-            plan->n_act = total;
-            plan->t_next = tn;
-            plan->nb = nb;
-            plan->S = S;
-            plan->jchunk = jc;
-            plan->steps += 1;
-            plan->sum_active += total;
-            plan->t_last = tn;
+            blk_plan_write(plan, total, tn, n, big_ok);
         }
     }
+}
+
+// The whole front end in one launch.  Work-group b owns chunk b: it takes
+// t_next from the kept chunk minima, counts its due particles, publishes
+// that count in pub[b] tagged with this step's number `tag` (release), then
+// predicts and packs its chunk, and only then waits for the counts of the
+// chunks before it (acquire) to place its part of the ordered block list.
+// Lower-numbered work-groups are dispatched first and never wait for higher
+// ones, so every wait ends; each wait is also bounded (kFrontSpin polls),
+// after which the plan records the failure (frozen = 2) and the step does
+// nothing.  The last work-group writes the plan.  The arithmetic of the
+// count, the compaction and the pack is the same as blk_count_pack_kernel +
+// blk_write_plan_kernel, so the same block list and records come out.
+template <int PREC>
+__global__ __launch_bounds__(kSelWG) void blk_front_kernel(int ch, int G, const int64_t* __restrict__ dt,
+                                                           const int64_t* __restrict__ gmin,
+                                                           int64_t* __restrict__ gmin_next,
+                                                           uint64_t* __restrict__ pub, uint32_t tag,
+                                                           int64_t* __restrict__ sel2, int32_t* __restrict__ idx,
+                                                           DevPlan* plan, PackArgs pa, int big_ok) {
+    __shared__ int64_t red[kSelWG / 64];
+    __shared__ int wsum[kSelWG / 64];
+    __shared__ int fail_sh;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int b = blockIdx.x;
+    const int n = pa.n;
+    int64_t m = INT64_MAX;
+    for (int g = tid; g < G; g += kSelWG) m = gmin[g] < m ? gmin[g] : m;
+    const int64_t tn = block_min_i64(m, red);
+    // due particles among this lane's `per` consecutive entries of the chunk
+    const int per = ch / kSelWG;
+    const int k0 = b * ch + tid * per;
+    int cnt = 0;
+    int64_t rest = INT64_MAX;
+    for (int u = 0; u < per; ++u) {
+        const int k = k0 + u;
+        if (k < n) {
+            const int64_t v = pa.t[k] + dt[k];
+            cnt += v == tn ? 1 : 0;
+            rest = (v != tn && v < rest) ? v : rest;
+        }
+    }
+    int incl = cnt;
+    for (int off = 1; off < 64; off <<= 1) {
+        const int o = __shfl_up(incl, off);
+        if (lane >= off) incl += o;
+    }
+    if (lane == 63) wsum[w] = incl;
+    if (tid == 0) fail_sh = 0;
+    rest = block_min_i64(rest, red);   // (its barriers also publish wsum and fail_sh)
+    int wbase = 0, c = 0;
+    for (int k = 0; k < kSelWG / 64; ++k) {
+        wbase += k < w ? wsum[k] : 0;
+        c += wsum[k];
+    }
+    const bool frozen = tn > plan->t_limit;
+    if (tid == 0) {
+        gmin_next[b] = frozen ? gmin[b] : rest;
+        if (b == 0) sel2[1] = tn;
+        __hip_atomic_store(&pub[b], ((uint64_t)tag << 32) | (uint32_t)c, __ATOMIC_RELEASE,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (frozen) {
+        if (b == G - 1) {
+            sel2[0] = 0;
+            plan->n_act = 0;
+            plan->frozen = 1;
+        }
+        return;
+    }
+    for (int k = b * ch + tid; k < min(n, (b + 1) * ch); k += kSelWG) pack_one<PREC>(pa, k, tn);
+    // counts of the chunks before this one
+    int64_t before = 0;
+    for (int g = tid; g < b; g += kSelWG) {
+        uint64_t v = 0;
+        int it = 0;
+        for (;;) {
+            v = __hip_atomic_load(&pub[g], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+            if ((uint32_t)(v >> 32) == tag) break;
+            if (++it >= kFrontSpin) {
+                fail_sh = 1;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        before += (int64_t)(uint32_t)v;
+    }
+    before = block_sum_i64(before, red);
+    if (fail_sh) {
+        // the step is void: no work-group waits for this one, and the host
+        // reports the failure at the end of the chunk
+        if (tid == 0) plan->frozen = 2;
+        if (b == G - 1 && tid == 0) {
+            sel2[0] = 0;
+            plan->n_act = 0;
+        }
+        return;
+    }
+    int64_t pos = before + wbase + incl - cnt;
+    for (int u = 0; u < per; ++u) {
+        const int k = k0 + u;
+        if (k < n && pa.t[k] + dt[k] == tn) idx[pos++] = k;
+    }
+    if (b == G - 1 && tid == 0) {
+        const int64_t total = before + c;
+        sel2[0] = total;
+        blk_plan_write(plan, total, tn, n, big_ok);
+    }
+}
+
+hipError_t launch_blk_front_fused(const PackArgs& pa, const int64_t* dt, int32_t* idx, int64_t* sel2, DevPlan* plan,
+                                  uint64_t* pub, uint32_t tag, int64_t* gmin, int64_t* gmin_next, bool need_min,
+                                  bool big_ok, hipStream_t st) {
+    const int n = pa.n;
+    if (n <= 0) return hipErrorInvalidValue;
+    const int ch = blk_chunk(n);
+    const int G = (n + ch - 1) / ch;
+    if (need_min) hipLaunchKernelGGL(blk_min_kernel, dim3(G), dim3(kSelWG), 0, st, n, ch, pa.t, dt, gmin);
+    if (pa.prec == 0)
+        hipLaunchKernelGGL(blk_front_kernel<0>, dim3(G), dim3(kSelWG), 0, st, ch, G, dt, gmin, gmin_next, pub, tag,
+                           sel2, idx, plan, pa, big_ok ? 1 : 0);
+    else
+        hipLaunchKernelGGL(blk_front_kernel<1>, dim3(G), dim3(kSelWG), 0, st, ch, G, dt, gmin, gmin_next, pub, tag,
+                           sel2, idx, plan, pa, big_ok ? 1 : 0);
+    return hipGetLastError();
 }
 
 int blk_chunk_size(int n) { return blk_chunk(n); }
@@ -482,12 +612,11 @@ __global__ __launch_bounds__(256) void init_dt_kernel(InitDtArgs a) {
     a.dt[i] = block_level(a.eta_s * na / nj, 0, 0, a.lmin, a.lmax);
 }
 
-// Block steps: the float64 reduction of the split partials (the same
-// lane-strided sums and butterfly as the wave-per-row split reduce, so the same
-// bits) fused with the corrector, one wave per active particle.  Without a
-// split the pairwise kernel has written the forces and only the corrector
-// runs.  Shared steps use it without a device plan, with the next step's
-// prediction and packing fused in as well (CorrectArgs.pack_next).
+// Block steps: the float64 reduction of the split partials fused with the
+// corrector.  Without a split the pairwise kernel has written the forces and
+// only the corrector runs.  Shared steps use it without a device plan, with
+// the next step's prediction and packing fused in as well
+// (CorrectArgs.pack_next).
 __global__ __launch_bounds__(256) void blk_reduce_correct_kernel(ReduceArgs r, CorrectArgs ca) {
     const DevPlan* pl = r.plan;
     const int n = pl ? (int)pl->n_act : r.ni, S = pl ? pl->S : r.S;
@@ -496,95 +625,63 @@ __global__ __launch_bounds__(256) void blk_reduce_correct_kernel(ReduceArgs r, C
         for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x) correct_one(ca, c);
         return;
     }
-    const int lane = threadIdx.x & 63;
-    if (n <= (int)gridDim.x && S > 64) {
-        // few particles, many ranges: a work-group (256 threads, as launched)
-        // per particle.  Thread k sums the ranges s = k, k + 256, ... in
-        // order; the lanes of a wave then combine by a fixed butterfly and
-        // the four waves in order.
-        __shared__ double wpart[4][6];
-        const int c = blockIdx.x;
-        if (c >= n) return;
-        const int tid = threadIdx.x, w = tid >> 6;
-        const float2* col = r.part + c;
-        const size_t qs = (size_t)n, rs = 7 * (size_t)n;
+    // Split reduce, 16 particles per work-group (256 threads, as launched):
+    // thread t takes particle p = t % 16 of the group and the ranges
+    // s = t / 16, t / 16 + 16, ... in order, so that for every (s, q) the
+    // group's 16 partial sums are one contiguous 128-byte line.  The 16
+    // range-lanes of a particle then combine in a fixed order: two butterfly
+    // steps inside each wave (lanes 16 and 32 apart), then the four waves in
+    // order.  The result depends only on S.
+    __shared__ double wpart[4][16][6];
+    const int tid = threadIdx.x, p = tid & 15, l = tid >> 4, w = tid >> 6;
+    const int ngroups = (n + 15) / 16;
+    const size_t qs = (size_t)n, rs = 7 * (size_t)n;
+    for (int g = blockIdx.x; g < ngroups; g += gridDim.x) {
+        const int c = g * 16 + p;
         double f[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-        int sp = tid;
-        for (; sp + 256 < S; sp += 512) {
-            float2 u[2][6];
+        if (c < n) {
+            const float2* col = r.part + c;
+            int sp = l;
+            for (; sp + 48 < S; sp += 64) {
+                float2 u[4][6];
 #pragma unroll
-            for (int h = 0; h < 2; ++h)
+                for (int h = 0; h < 4; ++h)
 #pragma unroll
-                for (int q = 0; q < 6; ++q) u[h][q] = col[(size_t)(sp + 256 * h) * rs + q * qs];
+                    for (int q = 0; q < 6; ++q) u[h][q] = col[(size_t)(sp + 16 * h) * rs + q * qs];
 #pragma unroll
-            for (int h = 0; h < 2; ++h)
+                for (int h = 0; h < 4; ++h)
+#pragma unroll
+                    for (int q = 0; q < 6; ++q) {
+                        f[q] += (double)u[h][q].x;
+                        f[q] += (double)u[h][q].y;
+                    }
+            }
+            for (; sp < S; sp += 16) {
+                float2 u[6];
+#pragma unroll
+                for (int q = 0; q < 6; ++q) u[q] = col[(size_t)sp * rs + q * qs];
 #pragma unroll
                 for (int q = 0; q < 6; ++q) {
-                    f[q] += (double)u[h][q].x;
-                    f[q] += (double)u[h][q].y;
+                    f[q] += (double)u[q].x;
+                    f[q] += (double)u[q].y;
                 }
-        }
-        for (; sp < S; sp += 256) {
-#pragma unroll
-            for (int q = 0; q < 6; ++q) {
-                const float2 u = col[(size_t)sp * rs + q * qs];
-                f[q] += (double)u.x;
-                f[q] += (double)u.y;
             }
         }
 #pragma unroll
         for (int q = 0; q < 6; ++q) {
-            for (int off = 32; off > 0; off >>= 1) f[q] += __shfl_xor(f[q], off);
-            if (lane == 0) wpart[w][q] = f[q];
+            f[q] += __shfl_xor(f[q], 16);
+            f[q] += __shfl_xor(f[q], 32);
+            if ((tid & 63) < 16) wpart[w][p][q] = f[q];
         }
         __syncthreads();
-        if (tid == 0) {
-            double g[6];
+        if (tid < 16 && c < n) {
+            double gq[6];
 #pragma unroll
-            for (int q = 0; q < 6; ++q) g[q] = r.G * (((wpart[0][q] + wpart[1][q]) + wpart[2][q]) + wpart[3][q]);
-            correct_core(ca, c, g, g + 3);
+            for (int q = 0; q < 6; ++q)
+                gq[q] = r.G * (((wpart[0][p][q] + wpart[1][p][q]) + wpart[2][p][q]) + wpart[3][p][q]);
+            correct_core(ca, c, gq, gq + 3);
         }
-        return;
-    }
-    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
-    for (int64_t w = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; w < n; w += nw) {
-        const int c = (int)w;
-        // the six quantities' loads of four ranges are in flight together; each
-        // quantity still sums its ranges s = lane, lane + 64, ... in order
-        double f[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-        const float2* col = r.part + c;
-        const size_t qs = (size_t)n, rs = 7 * (size_t)n;
-        int sp = lane;
-        for (; sp + 192 < S; sp += 256) {
-            float2 u[4][6];
-#pragma unroll
-            for (int h = 0; h < 4; ++h)
-#pragma unroll
-                for (int q = 0; q < 6; ++q) u[h][q] = col[(size_t)(sp + 64 * h) * rs + q * qs];
-#pragma unroll
-            for (int h = 0; h < 4; ++h)
-#pragma unroll
-                for (int q = 0; q < 6; ++q) {
-                    f[q] += (double)u[h][q].x;
-                    f[q] += (double)u[h][q].y;
-                }
-        }
-        for (; sp < S; sp += 64) {
-            float2 u[6];
-#pragma unroll
-            for (int q = 0; q < 6; ++q) u[q] = col[(size_t)sp * rs + q * qs];
-#pragma unroll
-            for (int q = 0; q < 6; ++q) {
-                f[q] += (double)u[q].x;
-                f[q] += (double)u[q].y;
-            }
-        }
-#pragma unroll
-        for (int q = 0; q < 6; ++q) {
-            for (int off = 32; off > 0; off >>= 1) f[q] += __shfl_xor(f[q], off);
-            f[q] = r.G * f[q];
-        }
-        if (lane == 0) correct_core(ca, c, f, f + 3);
+        __syncthreads();   // wpart is rewritten by the next group
     }
 }
 

@@ -83,6 +83,10 @@ constexpr int kBlkSmallTile = NB_BLK_SMALL_TJ, kBlkSmallWG = NB_BLK_SMALL_WG;
 constexpr int kBlkBigTile = 256, kBlkBigWG = 256;
 constexpr int kBlkBigMin = NB_BLK_BIG_MIN;   // 0: the large shape is never used
 constexpr int kBlkGrid = 2048;               // work-groups of each plan-driven launch
+// 1: the block-step front end runs as one launch (launch_blk_front_fused)
+#ifndef NB_BLK_FRONT_FUSED
+#define NB_BLK_FRONT_FUSED 1
+#endif
 
 // Arguments of the pairwise kernel (passed by value).
 struct ForceArgs {
@@ -225,6 +229,13 @@ int blk_scratch_words(int n);
 hipError_t launch_blk_front(const PackArgs& pa, const int64_t* dt, int32_t* idx, int64_t* sel2, DevPlan* plan,
                             int64_t* scratch, int64_t* gmin, int64_t* gmin_next, bool need_min, bool big_ok,
                             hipStream_t st);
+// The same front end as one launch (count, pack, ordered compaction and plan):
+// pub holds one word per chunk (zeroed once when allocated) in which each
+// step publishes its chunk counts tagged with `tag`, a number that differs
+// from step to step (never 0).
+hipError_t launch_blk_front_fused(const PackArgs& pa, const int64_t* dt, int32_t* idx, int64_t* sel2, DevPlan* plan,
+                                  uint64_t* pub, uint32_t tag, int64_t* gmin, int64_t* gmin_next, bool need_min,
+                                  bool big_ok, hipStream_t st);
 // Block steps: split reduce (when the plan has S > 1) fused with the corrector.
 // With r.plan NULL the block is particles 0 .. r.ni-1 and the split is r.S.
 hipError_t launch_blk_reduce_correct(const ReduceArgs& r, const CorrectArgs& ca, int grid, hipStream_t st);

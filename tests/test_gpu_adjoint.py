@@ -145,21 +145,38 @@ def test_plummer16k_gradient_identities(ctx):
 def test_plummer16k_gradient_against_oracle_adjoint(ctx):
     """The full differentiation workload (N = 16384, eps = 1e-3, 64 steps of
     1/128, checkpoints every 8, L = sum w.x(T)): every gradient component
-    against the float64 oracle's adjoint of the same run (the oracle adjoint
-    is pinned by central differences in the CPU tests).  About a minute of
-    host time for the oracle."""
+    against the float64 oracle's adjoint of the same run, and 32 seeded
+    components (11 of x0, 11 of v0, 10 masses) against central finite
+    differences (h = 1e-6) of the float64 oracle's run, stored in
+    tests/golden/adjoint16k_fd.json by make_adjoint16k_fd.py (oracle only).
+    About a minute of host time for the oracle adjoint."""
+    import json
+    import os
     import torch
     p = ics.workload("plummer16k_adjoint")
     eps, dt, steps = 1e-3, 1.0 / 128, 64
     w = ics.rng(ics.seed_for(3), 9).normal(size=(3, p.n))
+    with open(os.path.join(os.path.dirname(__file__), "golden", "adjoint16k_fd.json")) as f:
+        fd = json.load(f)
+    assert fd["recipe"]["n"] == p.n and fd["h"] == 1e-6 and len(fd["entries"]) == 32
     rx, rv, rm = oracle.hermite_shared_adjoint(p.pos, p.vel, p.mass, eps, dt, steps, w)
     X, V, M, W = dev(p.pos), dev(p.vel), dev(p.mass), dev(w)
     for prec, bar in (("ds", 1e-4), ("fp32", 1e-3)):
         _, _, ck = ctx.shared_run(X, V, M, eps, dt, steps, prec=prec, ckpt_every=8)
         gx, gv, gm = ctx.shared_adjoint(X, V, M, eps, dt, steps, ck, W, prec=prec, ckpt_every=8)
         torch.cuda.synchronize()
-        st = {"gx0": rel_err_stats(host(gx), rx), "gv0": rel_err_stats(host(gv), rv),
-              "gm": scaled_err_stats(host(gm), rm)}
+        gx, gv, gm = host(gx), host(gv), host(gm)
+        st = {"gx0": rel_err_stats(gx, rx), "gv0": rel_err_stats(gv, rv),
+              "gm": scaled_err_stats(gm, rm)}
         print(prec, "N=16384", {k: f"p99={v['p99']:.2e} max={v['max']:.2e}" for k, v in st.items()}, flush=True)
         for k in st:
             assert st[k]["p99"] <= bar, (prec, k, st[k])
+        # against the oracle's central differences, element by element
+        worst = 0.0
+        for e in fd["entries"]:
+            ana = {"x": gx, "v": gv}[e["kind"]][e["c"], e["i"]] if e["kind"] != "m" else gm[e["i"]]
+            err = abs(ana - e["fd"]) / max(abs(e["fd"]), 1e-3)
+            worst = max(worst, err)
+            if prec == "ds":
+                assert err <= 1e-3, (e, ana)
+        print(prec, "N=16384 worst relative mismatch against finite differences", f"{worst:.2e}", flush=True)

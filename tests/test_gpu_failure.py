@@ -95,6 +95,7 @@ def test_injected_allocation_failure_force(monkeypatch):
         torch.cuda.synchronize()
         assert all(bool((t == 7.0).all()) for t in out)
         a, j, pt = c.force(X, V, X, V, M, 0.01, i_self=S)
+        monkeypatch.delenv("NBODY_DEBUG_FAIL_ALLOC")
         c2 = nb.Context(0)
         try:
             b = c2.force(X, V, X, V, M, 0.01, i_self=S)

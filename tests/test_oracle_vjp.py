@@ -108,3 +108,28 @@ def test_vjp_null_cotangents_equal_zero_cotangents():
                           iself=np.arange(n))
     for a, b in zip(r1, r2):
         np.testing.assert_array_equal(a, b)
+
+
+def test_stored_central_differences_match_adjoint_at_full_size():
+    """tests/golden/adjoint16k_fd.json (written from the oracle alone by
+    make_adjoint16k_fd.py): at the full differentiation recipe (N = 16384,
+    eps = 1e-3, 64 Hermite steps of 1/128, L = sum w.x(T)), central differences
+    of L with h = 1e-6 agree with the oracle's adjoint of the same run, 32
+    seeded coordinates.  Positions and velocities: the difference is set by
+    the rounding noise of L over 2h, about 1e-6 of the gradients' rms.
+    Masses (m = 1/16384): h moves a mass by 1.6 %, so the O(h^2) truncation
+    of the central difference dominates; the bar is 1e-3 of the rms."""
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(__file__), "golden", "adjoint16k_fd.json")) as f:
+        d = json.load(f)
+    assert d["recipe"]["n"] == 16384 and d["h"] == 1e-6
+    kinds = {k: [e for e in d["entries"] if e["kind"] == k] for k in "xvm"}
+    assert len(kinds["x"]) >= 8 and len(kinds["v"]) >= 8 and len(kinds["m"]) >= 8
+    for k, bar in (("x", 5e-6), ("v", 5e-6), ("m", 1e-3)):
+        fd = np.array([e["fd"] for e in kinds[k]])
+        ad = np.array([e["oracle_adjoint"] for e in kinds[k]])
+        rms = np.sqrt(np.mean(fd * fd))
+        err = np.abs(fd - ad) / rms
+        assert err.max() <= bar, (k, err.max())
+        assert np.median(np.abs(fd - ad) / np.abs(fd)) <= 1e-5, k
