@@ -304,6 +304,33 @@ def batched_timing(ctx, prec, steps=32, graph=True):
             "per_cluster_Gint_s": round(tot / t_per / 1e9, 1)}
 
 
+def batched_probe(prec, steps=2):
+    """The batched workload without the autotuner, the per-cluster runs or a
+    graph: one force evaluation of the 512 clusters and `steps` eagerly
+    launched shared Hermite steps in the default launch shape (a short run
+    for profiler counter passes)."""
+    import numpy as np
+    import torch
+    import nbody_inputs as ics
+    import paper_0707_0438_amd as nb
+    off, eps, p = ics.clusters(512, ics.seed_for(4))
+    X, V, M = (torch.from_numpy(a).to("cuda") for a in (p.pos, p.vel, p.mass))
+    O, E = torch.from_numpy(off).to("cuda"), torch.from_numpy(eps).to("cuda")
+    ctx = nb.Context(0)
+    try:
+        a, j, _ = ctx.force_batched(X, V, M, O, E, prec=prec)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.batch_hermite(X, V, a, j, M, O, E, 1.0 / 256, steps, prec=prec, use_graph=False)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+    finally:
+        ctx.close()
+    inter = float((np.diff(off).astype(np.float64) ** 2).sum()) * steps
+    return {"workload": "clusters512_batched (default shape, eager launches)", "prec": prec, "steps": steps,
+            "wall_s": round(wall, 4), "Gint_s": round(inter / wall / 1e9, 1)}
+
+
 def kinds_timing(ctx, X, V, M, eps, prec, full_kernel_ms, reps=2):
     """The force-only (acceleration + potential, 38 conventional flops per
     interaction) and nearest-neighbour evaluations on the same N = 2^20
@@ -496,12 +523,18 @@ def main():
     ap.add_argument("--extras", default="batched,adjoint,kinds,shard,block,shared1k",
                     help="comma list of extra measurements (batched, adjoint, kinds, shard, block, shared1k) or 'none'")
     ap.add_argument("--report-every", type=float, default=0.0)
+    ap.add_argument("--batched-probe", action="store_true",
+                    help="only run the batched clusters briefly, eagerly, in the default shape "
+                         "(profiler counter passes) and print its JSON")
     ap.add_argument("--no-graph", action="store_true",
                     help="launch the batched steps eagerly only (no hipGraph capture), e.g. under "
                          "profiler counter passes")
     args = ap.parse_args()
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.batched_probe:
+        print(json.dumps(batched_probe(args.prec)), flush=True)
         return
     if args.block_run:
         out = block_run(args.n if args.n != (1 << 20) else 65536, args.t_end, ["fp32", "ds"], args.report_every)

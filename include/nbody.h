@@ -109,7 +109,23 @@ typedef struct {
 /* Create a context on HIP device `device` (the caller's current device is
  * restored).  tune_cache_path: JSON file the autotuner reads and writes, or
  * NULL for $NBODY_TUNE_CACHE (unset: no persistent cache).  On failure *ctx
- * is set to NULL and the code is returned (details cannot be queried). */
+ * is set to NULL and the code is returned (details cannot be queried).
+ * Environment read here:
+ *  NBODY_TRACE=<path>  append one JSON line per Hermite step of this
+ *    context's integrators to <path>: {"mode": "block" | "shared", "step",
+ *    "t_ticks", "t", "n_act", "shape": "small" | "large" (block steps: the
+ *    launch shape the device plan chose; shared steps: "direct"), "groups"
+ *    (i-groups of the block step), "ranges" (j-ranges)}.  Block steps are
+ *    recorded on the device and written at each chunk's plan readback (no
+ *    extra synchronisation per step).  A path that cannot be opened turns
+ *    tracing off.
+ *  NBODY_FORCE_TILE=tile_j,ipt,wg[,split[,jsrc[,unroll[,waves]]]]  pin the
+ *    launch shape of the pairwise kernel (nbody_tile fields; omitted ones
+ *    0), as nbody_set_tile does, for each precision that has the shape
+ *    compiled; NBODY_ERR_ARG from nbody_create when no precision has it.
+ *  NBODY_DEBUG_FAIL_ALLOC=<k>  the k-th device allocation of the context
+ *    fails with NBODY_ERR_NOMEM (failure-path testing).
+ *  NBODY_DEBUG_SELF_CHECK=1  see nbody_force. */
 int nbody_create(nbody_ctx **ctx, int device, const char *tune_cache_path);
 
 /* Release the context and all of its device memory.  NULL is accepted. */

@@ -47,6 +47,9 @@ struct nbody_ctx {
     int alloc_count = 0;
     int fail_alloc_at = 0;    // debug: NBODY_DEBUG_FAIL_ALLOC=k fails the k-th allocation
     bool self_check = false;  // debug: NBODY_DEBUG_SELF_CHECK=1 verifies self rows (synchronises)
+    // NBODY_TRACE=<path>: one JSON line per Hermite step appended to that file
+    std::string trace_path;
+    FILE* trace = nullptr;
     // kernel timing: event pairs recorded around each pairwise-kernel launch
     bool timing = false;
     std::vector<hipEvent_t> ev;   // 2 per launch
@@ -73,6 +76,8 @@ struct nbody_hermite {
     int64_t spack_tn = -1;    // tick those records are valid for (-1: none)
     int64_t* gmin2 = nullptr; // block steps: two arrays of chunk minima of t + dt (this step's, next)
     uint64_t* gpub = nullptr; // block steps: per-chunk published counts of the fused front end
+    unsigned* gcnt = nullptr; // block steps: per-group range counters of the one-launch step (zero between steps)
+    TraceRec* ring = nullptr; // block steps: per-step records for NBODY_TRACE (device)
     uint32_t front_tag = 0;   // tag of the last enqueued block step (never 0 once used)
     int gpar = 0;             // which of the two holds this step's
     bool gmin_ok = false;     // false: recompute this step's before use
@@ -335,21 +340,26 @@ static int run_force(nbody_ctx* c, hipStream_t st, int prec, double G, double ep
     return NBODY_OK;
 }
 
-static int pack_rows(nbody_ctx* c, hipStream_t st, int prec, int64_t n, const nbody_src& s,
-                     bool with_m, DevBuf& dst) {
-    const size_t bytes = sizeof(float4) * (size_t)rec_words(prec) * (size_t)std::max<int64_t>(n, 1);
-    int rc = dev_alloc(c, dst, bytes);
-    if (rc) return rc;
+static int pack_into(nbody_ctx* c, hipStream_t st, int prec, int64_t n, const nbody_src& s, bool with_m,
+                     float4* dst) {
     PackArgs p{};
     p.n = (int)n;
     p.prec = prec;
     p.x = s.x; p.y = s.y; p.z = s.z;
     p.vx = s.vx; p.vy = s.vy; p.vz = s.vz;
     p.m = with_m ? s.m : nullptr;
-    p.out = (float4*)dst.p;
+    p.out = dst;
     hipError_t e = launch_pack(p, st);
     if (e != hipSuccess) return hip_err(c, e, "pack launch");
     return NBODY_OK;
+}
+
+static int pack_rows(nbody_ctx* c, hipStream_t st, int prec, int64_t n, const nbody_src& s,
+                     bool with_m, DevBuf& dst) {
+    const size_t bytes = sizeof(float4) * (size_t)rec_words(prec) * (size_t)std::max<int64_t>(n, 1);
+    int rc = dev_alloc(c, dst, bytes);
+    if (rc) return rc;
+    return pack_into(c, st, prec, n, s, with_m, (float4*)dst.p);
 }
 
 static bool same_src(const nbody_src& a, const nbody_src& b) {
@@ -385,6 +395,26 @@ int nbody_create(nbody_ctx** ctx, int device, const char* tune_cache_path) {
     if (!c) return NBODY_ERR_NOMEM;
     if (const char* f = getenv("NBODY_DEBUG_FAIL_ALLOC")) c->fail_alloc_at = atoi(f);
     if (const char* f = getenv("NBODY_DEBUG_SELF_CHECK")) c->self_check = atoi(f) != 0;
+    if (const char* f = getenv("NBODY_TRACE")) c->trace_path = f;
+    if (const char* f = getenv("NBODY_FORCE_TILE")) {
+        // tile_j,ipt,wg[,split[,jsrc[,unroll[,waves]]]]: the launch shape of
+        // every evaluation of the precisions that compile it
+        int v[7] = {0, 0, 0, 0, 0, 0, 0};
+        const int got = sscanf(f, "%d,%d,%d,%d,%d,%d,%d", &v[0], &v[1], &v[2], &v[3], &v[4], &v[5], &v[6]);
+        const nbody_tile t{v[0], v[1], v[2], v[3], v[4], v[5], v[6]};
+        bool any = false;
+        if (got >= 3 && t.split >= 0 && t.split <= 4096)
+            for (int prec = 0; prec < 2; ++prec)
+                if (force_variant_exists(prec, t.ipt, t.tile_j, t.wg, t.jsrc, t.unroll, t.waves, false)) {
+                    c->override_tile[prec] = t;
+                    c->have_override[prec] = true;
+                    any = true;
+                }
+        if (!any) {
+            delete c;
+            return NBODY_ERR_ARG;
+        }
+    }
     const char* path = tune_cache_path ? tune_cache_path : getenv("NBODY_TUNE_CACHE");
     if (path && *path) c->tune.set_path(path);
     if (device >= 0) {
@@ -419,6 +449,7 @@ int nbody_destroy(nbody_ctx* c) {
         for (hipEvent_t x : c->gev)
             if (x) (void)hipEventDestroy(x);
         if (c->gstream) (void)hipStreamDestroy(c->gstream);
+        if (c->trace) fclose(c->trace);
         DevBuf* bufs[] = {&c->ipack, &c->jpack, &c->part, &c->sel, &c->scratch64,
                           &c->vrec_i, &c->vrec_j, &c->vpart, &c->integ, &c->hist, &c->bplan,
                           &c->bstate, &c->lf};
@@ -437,25 +468,37 @@ static int need_device(nbody_ctx* c) {
     return NBODY_OK;
 }
 
+// Split-partial bytes of the shapes the next calls would take for up to
+// max_i i-particles against max_j j: evaluated at max_i and at every power
+// of two below it (the long-evaluation rule keeps S x n_i about constant, so
+// the largest is near one of these).  Host arithmetic only.
+static size_t reserve_part_bytes(nbody_ctx* c, int64_t max_i, int64_t max_j) {
+    const int64_t ni = std::max<int64_t>(max_i, 1), nj = std::max<int64_t>(max_j, 1);
+    size_t part = 0;
+    for (int prec = 0; prec < 2; ++prec) {
+        int64_t n = ni;
+        for (;;) {
+            const nbody_tile t = pick_tile(c, prec, n, nj);
+            int nb, S, jc;
+            split_plan(n, nj, t.wg * t.ipt, t.tile_j, t.split, &nb, &S, &jc);
+            if (S > 1) part = std::max(part, sizeof(float2) * 8 * (size_t)S * (size_t)n);
+            if (n <= 1) break;
+            // the largest power of two below n (n strictly decreases)
+            const int64_t p2 = (int64_t)1 << (63 - __builtin_clzll((unsigned long long)n));
+            n = p2 < n ? p2 : n / 2;
+        }
+    }
+    return part;
+}
+
 int nbody_reserve(nbody_ctx* c, int64_t max_i, int64_t max_j) {
     if (!c) return NBODY_ERR_ARG;
     if (max_i < 0 || max_j < 0 || max_i > kMaxN || max_j > kMaxN)
         return set_err(c, NBODY_ERR_ARG, "reserve: sizes must be in [0, 2^31-1]");
+    const size_t part = reserve_part_bytes(c, max_i, max_j);
     if (int rc = need_device(c)) return rc;
     DeviceGuard g(c->device);
     const size_t ni = (size_t)std::max<int64_t>(max_i, 1), nj = (size_t)std::max<int64_t>(max_j, 1);
-    // split partial sums of the shapes the next calls would take: at max_i
-    // and at every power of two below it (the long-evaluation rule keeps
-    // S x n_i about constant, so the largest is near one of these)
-    size_t part = 0;
-    for (int prec = 0; prec < 2; ++prec)
-        for (int64_t n = (int64_t)ni; n >= 1; n = n == (int64_t)ni ? (int64_t)1 << (63 - __builtin_clzll(n)) : n / 2) {
-            const nbody_tile t = pick_tile(c, prec, n, (int64_t)nj);
-            int nb, S, jc;
-            split_plan(n, (int64_t)nj, t.wg * t.ipt, t.tile_j, t.split, &nb, &S, &jc);
-            if (S > 1) part = std::max(part, sizeof(float2) * 8 * (size_t)S * (size_t)n);
-            if (n == 1) break;
-        }
     int rc = dev_alloc(c, c->ipack, sizeof(float4) * kRecDS * ni);
     if (!rc) rc = dev_alloc(c, c->jpack, sizeof(float4) * kRecDS * nj);
     if (!rc && part > 0) rc = dev_alloc(c, c->part, part);
@@ -726,7 +769,8 @@ int nbody_hermite_create(nbody_ctx* c, nbody_hermite** hp, int64_t n, const nbod
                          r256(sizeof(double) * 2) + r256(sizeof(DevPlan)) +
                          (o->shared_dt_log2 != 0 ? r256(sizeof(float4) * kRecDS * nn) : 0) +
                          r256(sizeof(int64_t) * blk_scratch_words((int)n)) +
-                         r256(sizeof(uint64_t) * blk_scratch_words((int)n) / 2);
+                         r256(sizeof(uint64_t) * blk_scratch_words((int)n) / 2) +
+                         r256(sizeof(unsigned) * blk_step_groups((int)n)) + r256(sizeof(TraceRec) * kTraceCap);
     ++c->alloc_count;
     if (c->fail_alloc_at > 0 && c->alloc_count == c->fail_alloc_at) {
         delete h;
@@ -757,8 +801,12 @@ int nbody_hermite_create(nbody_ctx* c, nbody_hermite** hp, int64_t n, const nbod
     if (o->shared_dt_log2 != 0) h->spack = (float4*)take(sizeof(float4) * kRecDS * nn);   // shared steps only
     h->gmin2 = (int64_t*)take(sizeof(int64_t) * blk_scratch_words((int)n));
     h->gpub = (uint64_t*)take(sizeof(uint64_t) * blk_scratch_words((int)n) / 2);
-    // the published counts start untagged (tag 0 is never used)
+    h->gcnt = (unsigned*)take(sizeof(unsigned) * blk_step_groups((int)n));
+    h->ring = (TraceRec*)take(sizeof(TraceRec) * kTraceCap);
+    // the published counts start untagged (tag 0 is never used); the group
+    // counters start at zero
     e = launch_fill_i64((int64_t*)h->gpub, blk_scratch_words((int)n) / 2, 0, nullptr);
+    if (e == hipSuccess) e = launch_fill_i32((int*)h->gcnt, blk_step_groups((int)n), 0, nullptr);
     if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
     if (e != hipSuccess) {
         (void)hipFree(h->block);
@@ -832,12 +880,55 @@ int nbody_hermite_set_state(nbody_hermite* h, hipStream_t st, nbody_src P) {
 }
 
 
+// NBODY_TRACE: append one JSON line per step to the trace file (opened on
+// first use; a file that cannot be opened turns tracing off for the context).
+static FILE* trace_file(nbody_ctx* c) {
+    if (c->trace_path.empty()) return nullptr;
+    if (!c->trace) {
+        c->trace = fopen(c->trace_path.c_str(), "a");
+        if (!c->trace) c->trace_path.clear();
+    }
+    return c->trace;
+}
+
+static void trace_line(nbody_ctx* c, const char* mode, int64_t step, int64_t t_next, int64_t n_act,
+                       const char* shape, int groups, int ranges) {
+    FILE* f = trace_file(c);
+    if (!f) return;
+    fprintf(f,
+            "{\"mode\": \"%s\", \"step\": %lld, \"t_ticks\": %lld, \"t\": %.17g, \"n_act\": %lld, "
+            "\"shape\": \"%s\", \"groups\": %d, \"ranges\": %d}\n",
+            mode, (long long)step, (long long)t_next, (double)t_next * kTick, (long long)n_act, shape, groups,
+            ranges);
+}
+
+// The block steps from `after` (exclusive) up to the plan's count, from the
+// device ring (synchronises `st`; tracing only).
+static int trace_block_steps(nbody_hermite* h, hipStream_t st, int64_t after, int64_t upto) {
+    nbody_ctx* c = h->ctx;
+    if (!trace_file(c) || upto <= after) return NBODY_OK;
+    TraceRec r[kTraceCap];
+    hipError_t e = hipMemcpyAsync(r, h->ring, sizeof r, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_err(c, e, "trace read");
+    const int64_t from = std::max(after + 1, upto - kTraceCap + 1);
+    for (int64_t k = from; k <= upto; ++k) {
+        const TraceRec& x = r[(k - 1) % kTraceCap];
+        if (x.step != k) continue;
+        const bool small = x.shape == 0;
+        trace_line(c, "block", x.step, x.t_next, x.n_act, small ? "small" : "large", x.nb, x.S);
+    }
+    fflush(c->trace);
+    return NBODY_OK;
+}
+
 static int plan_reset(nbody_hermite* h, hipStream_t st, int64_t t_limit) {
     DevPlan p{};
     p.steps = h->steps;
     p.sum_active = h->sum_active;
     p.t_last = h->t_ticks;
     p.t_limit = t_limit;
+    p.ring = h->ctx->trace_path.empty() ? nullptr : h->ring;
     hipError_t e = hipMemcpyAsync(h->plan, &p, sizeof p, hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) return hip_err(h->ctx, e, "plan write");
@@ -949,6 +1040,10 @@ static int hermite_step_shared(nbody_hermite* h, hipStream_t st, int64_t t_limit
     h->t_ticks = tn;
     h->steps += 1;
     h->sum_active += n;
+    if (trace_file(c)) {
+        trace_line(c, "shared", h->steps, tn, n, "direct", 0, S);
+        fflush(c->trace);
+    }
     return NBODY_OK;
 }
 
@@ -999,6 +1094,18 @@ static int hermite_enqueue_block(nbody_hermite* h, hipStream_t st) {
     for (int q = 0; q < 7; ++q) a.out[q] = h->f[q];
     a.part = (float2*)c->part.p;
     a.plan = h->plan;
+#if NB_BLK_STEP_FUSED
+    {
+        CorrectArgs ca = correct_args(h, n);
+        ca.gmin_next = gmin_next;
+        ca.gch = blk_chunk_size(n);
+        e = launch_blk_step(p, eps0, a, ca, h->gcnt, st);
+        if (e != hipSuccess) return hip_err(c, e, "block step launch");
+        h->gpar ^= 1;
+        h->gmin_ok = true;
+        return NBODY_OK;
+    }
+#endif
     e = launch_force_plan(p, eps0, a, st);
     if (e != hipSuccess) return hip_err(c, e, "force launch");
     ReduceArgs r{};
@@ -1050,8 +1157,10 @@ static int hermite_block_run(nbody_hermite* h, hipStream_t st, int64_t t_limit, 
         }
         done += k;
         DevPlan p;
+        const int64_t before = h->steps;
         rc = plan_read(h, st, &p);
         if (rc) return rc;
+        if ((rc = trace_block_steps(h, st, before, p.steps))) return rc;
         if (p.frozen == 2)
             return set_err(h->ctx, NBODY_ERR_DEVICE,
                            "block step: a wait for the chunk counts of the front end did not end");

@@ -252,10 +252,30 @@ constexpr int kFrontSpin = 1 << 20;
 __device__ __forceinline__ void blk_plan_write(DevPlan* plan, int64_t total, int64_t tn, int n, int big_ok) {
     const int big = big_ok && kBlkBigMin > 0 && total >= kBlkBigMin;
     int nb, S, jc;
+#if NB_BLK_STEP_FUSED
+    if (big) {
+        split_plan(total, n, kBlkStepWG, kBlkBigTile, 0, &nb, &S, &jc, 1);
+        if (S > kBlkBigMaxS) split_plan(total, n, kBlkStepWG, kBlkBigTile, kBlkBigMaxS, &nb, &S, &jc, 1);
+    } else {
+        // j-ranges: enough (group, range) items to spread over the device
+        // (about kJparItems), at most kJparMaxS ranges and at least one
+        // sweep of kBlkStepWG x kJparJPL records each
+        const int sweep = kBlkStepWG * kJparJPL;
+        nb = (int)((total + kJparIG - 1) / kJparIG);
+        int64_t smax = ((int64_t)n + sweep - 1) / sweep;
+        smax = smax < kJparMaxS ? smax : kJparMaxS;
+        int64_t sw = ((int64_t)kJparItems + nb - 1) / nb;
+        sw = sw < smax ? sw : smax;
+        sw = sw > 1 ? sw : 1;
+        jc = (int)((((int64_t)n + sw - 1) / sw + sweep - 1) / sweep * sweep);
+        S = (int)(((int64_t)n + jc - 1) / jc);
+    }
+#else
     if (big)
         split_plan(total, n, kBlkBigWG, kBlkBigTile, 0, &nb, &S, &jc, 1);
     else
         split_plan(total, n, kBlkSmallWG, kBlkSmallTile, 0, &nb, &S, &jc, total <= kBlkTinyMax ? 1 : kBlkMinTiles);
+#endif
     plan->shape = big;
     plan->n_act = total;
     plan->t_next = tn;
@@ -265,6 +285,16 @@ __device__ __forceinline__ void blk_plan_write(DevPlan* plan, int64_t total, int
     plan->steps += 1;
     plan->sum_active += total;
     plan->t_last = tn;
+    if (TraceRec* r = plan->ring) {
+        TraceRec& e = r[(plan->steps - 1) % kTraceCap];
+        e.step = plan->steps;
+        e.t_next = tn;
+        e.n_act = total;
+        e.shape = big;
+        e.nb = nb;
+        e.S = S;
+        e.pad_ = 0;
+    }
 }
 
 // gmin holds this step's chunk minima.  gmin_next receives, per chunk, the
@@ -507,90 +537,10 @@ hipError_t launch_blk_front(const PackArgs& pa, const int64_t* dt, int32_t* idx,
     return hipGetLastError();
 }
 
-__device__ __forceinline__ double norm3(double a, double b, double c) { return sqrt(a * a + b * b + c * c); }
-
-// Corrector for the active block (Makino & Aarseth 1992 Hermite scheme):
-// with D = dt_i, the predicted state recomputed exactly as in the pack,
-//   a2 = (-6 (a0 - a1) - D (4 j0 + 2 j1)) / D^2
-//   a3 = (12 (a0 - a1) + 6 D (j0 + j1)) / D^3
-//   x1 = x_p + a2 D^4/24 + a3 D^5/120,  v1 = v_p + a2 D^3/6 + a3 D^4/24,
-// then the Aarseth criterion with a2 carried to the new time, and the
-// power-of-two level rule.
-__device__ __forceinline__ void correct_core(const CorrectArgs& a, int c, const double* a1in, const double* j1in);
-__device__ __forceinline__ void correct_one(const CorrectArgs& a, int c) {
-    double a1[3], j1[3];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        a1[k] = a.f[k][c];
-        j1[k] = a.f[3 + k][c];
-    }
-    correct_core(a, c, a1, j1);
-}
-
 __global__ __launch_bounds__(256) void correct_kernel(CorrectArgs a) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= a.n_act) return;
     correct_one(a, c);
-}
-
-__device__ __forceinline__ void correct_core(const CorrectArgs& a, int c, const double* a1in,
-                                             const double* j1in) {
-    const int i = a.idx ? a.idx[c] : c;
-    const int64_t tn = a.tnext ? *a.tnext : a.tn;
-    if (c == 0 && a.tnow) *a.tnow = tn;
-    const double D = (double)a.dt[i] * kTick;
-    double* X[3] = {a.x, a.y, a.z};
-    double* V[3] = {a.vx, a.vy, a.vz};
-    double* A[3] = {a.ax, a.ay, a.az};
-    double* J[3] = {a.jx, a.jy, a.jz};
-    const double Dp = (double)(tn - a.t[i]) * kTick;   // equals D for an active particle
-    double a1[3], j1[3], a2[3], a3[3];
-    const double iD = 1.0 / D, iD2 = iD * iD, iD3 = iD2 * iD;
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        double xp, vp;
-        predict1(X[k][i], V[k][i], A[k][i], J[k][i], Dp, xp, vp);
-        a1[k] = a1in[k];
-        j1[k] = j1in[k];
-        const double a0 = A[k][i], j0 = J[k][i];
-        const double da = a0 - a1[k];
-        a2[k] = (-6.0 * da - D * (4.0 * j0 + 2.0 * j1[k])) * iD2;
-        a3[k] = (12.0 * da + 6.0 * D * (j0 + j1[k])) * iD3;
-        const double D2 = D * D, D3 = D2 * D, D4 = D3 * D;
-        X[k][i] = xp + D4 * (a2[k] * (1.0 / 24.0) + D * a3[k] * (1.0 / 120.0));
-        V[k][i] = vp + D3 * (a2[k] * (1.0 / 6.0) + D * a3[k] * (1.0 / 24.0));
-        A[k][i] = a1[k];
-        J[k][i] = j1[k];
-    }
-    a.t[i] = tn;
-    if (a.pack_next) {
-        // the next shared step's record of this particle, from the state just
-        // written (read back through memory, as a pack pass reads it)
-        PackArgs p{};
-        p.x = a.x; p.y = a.y; p.z = a.z;
-        p.vx = a.vx; p.vy = a.vy; p.vz = a.vz;
-        p.m = a.m;
-        p.ax = a.ax; p.ay = a.ay; p.az = a.az;
-        p.jx = a.jx; p.jy = a.jy; p.jz = a.jz;
-        p.t = a.t;
-        p.out = a.pack_next;
-        if (a.pack_prec == 1)
-            pack_one<1>(p, i, a.tn_next);
-        else
-            pack_one<0>(p, i, a.tn_next);
-    }
-    if (!a.shared) {
-        const double b0 = a2[0] + a3[0] * D, b1 = a2[1] + a3[1] * D, b2 = a2[2] + a3[2] * D;
-        const double na = norm3(a1[0], a1[1], a1[2]), nj = norm3(j1[0], j1[1], j1[2]);
-        const double n2 = norm3(b0, b1, b2), n3 = norm3(a3[0], a3[1], a3[2]);
-        const double crit = sqrt(a.eta * (na * n2 + nj * nj) / (nj * n3 + n2 * n2));
-        const int64_t dtn = block_level(crit, a.dt[i], tn, a.lmin, a.lmax);
-        a.dt[i] = dtn;
-        // the next block time of this particle joins its chunk's minimum
-        // (ticks are non-negative, so the unsigned minimum is the minimum)
-        if (a.gmin_next)
-            atomicMin((unsigned long long*)&a.gmin_next[i / a.gch], (unsigned long long)(tn + dtn));
-    }
 }
 
 hipError_t launch_correct(const CorrectArgs& a, hipStream_t st) {

@@ -54,6 +54,15 @@ __host__ __device__ inline void split_plan(int64_t ni, int64_t nj, int per_blk, 
     *jchunk_out = (int)jchunk;
 }
 
+// One block step as the plan recorded it (NBODY_TRACE): written by the
+// device into a ring of kTraceCap records, read by the host at each chunk's
+// plan readback (a chunk holds at most kTraceCap steps).
+struct TraceRec {
+    int64_t step, t_next, n_act;
+    int shape, nb, S, pad_;
+};
+constexpr int kTraceCap = 64;
+
 // Block-step state the device keeps between launches (one per driver).
 struct DevPlan {
     int64_t n_act;              // block size after the end-time gate (0: nothing to do)
@@ -63,6 +72,7 @@ struct DevPlan {
     int64_t t_limit;            // end time of the current advance (ticks)
     int nb, S, jchunk, frozen;  // launch geometry; frozen = the gate stopped a step
     int shape, pad_;            // launch shape of the block: 0 small, 1 large (see below)
+    TraceRec* ring;             // per-step records (NULL: not traced)
 };
 
 // Launch shapes of the plan-driven pairwise kernel (block steps).  Small
@@ -83,6 +93,28 @@ constexpr int kBlkSmallTile = NB_BLK_SMALL_TJ, kBlkSmallWG = NB_BLK_SMALL_WG;
 constexpr int kBlkBigTile = 256, kBlkBigWG = 256;
 constexpr int kBlkBigMin = NB_BLK_BIG_MIN;   // 0: the large shape is never used
 constexpr int kBlkGrid = 2048;               // work-groups of each plan-driven launch
+// 1: after the front end a block step is one launch (blk_step_kernel):
+// 256-lane work-groups; small blocks are j-parallel, in groups of kJparIG
+// i-particles against j-ranges swept 256 x kJparJPL records at a time;
+// large blocks take at most kBlkBigMaxS j-ranges; the last work-group of a
+// group reduces its partials and runs the corrector.  Partials stay within
+// 7 x (n + 4096) (small) and 7 x (2048 x 256 + n) (large) float2.  0: pairwise launches by shape, then a
+// split-reduce + corrector launch.
+#ifndef NB_BLK_STEP_FUSED
+#define NB_BLK_STEP_FUSED 0
+#endif
+constexpr int kBlkStepWG = 256;
+constexpr int kJparIG = 2;
+constexpr int kJparJPL = 4;
+constexpr int kBlkBigMaxS = 64;
+constexpr int kJparItems = 2048;   // (group, range) items a small block aims for
+constexpr int kJparMaxS = 64;      // j-ranges of a small block at most
+// waves per SIMD asked of the compiler for blk_step_kernel (a register cap:
+// the large-block tile loop keeps the occupancy of its direct-launch form)
+#ifndef NB_BLK_STEP_WAVES
+#define NB_BLK_STEP_WAVES 5
+#endif
+constexpr int kBlkStepWaves = NB_BLK_STEP_WAVES;
 // 1: the block-step front end runs as one launch (launch_blk_front_fused)
 #ifndef NB_BLK_FRONT_FUSED
 #define NB_BLK_FRONT_FUSED 1
@@ -236,6 +268,12 @@ hipError_t launch_blk_front(const PackArgs& pa, const int64_t* dt, int32_t* idx,
 hipError_t launch_blk_front_fused(const PackArgs& pa, const int64_t* dt, int32_t* idx, int64_t* sel2, DevPlan* plan,
                                   uint64_t* pub, uint32_t tag, int64_t* gmin, int64_t* gmin_next, bool need_min,
                                   bool big_ok, hipStream_t st);
+// One-launch block step after the front end (NB_BLK_STEP_FUSED): pairwise sums
+// of the plan's block, split reduce and corrector.  gcnt: one counter per
+// group, zero between launches (blk_step_groups(n) words).
+hipError_t launch_blk_step(int prec, bool eps0, const ForceArgs& a, const CorrectArgs& ca, unsigned* gcnt,
+                           hipStream_t st);
+inline int blk_step_groups(int n) { return (n + kJparIG - 1) / kJparIG + 1; }
 // Block steps: split reduce (when the plan has S > 1) fused with the corrector.
 // With r.plan NULL the block is particles 0 .. r.ni-1 and the split is r.S.
 hipError_t launch_blk_reduce_correct(const ReduceArgs& r, const CorrectArgs& ca, int grid, hipStream_t st);
@@ -368,6 +406,86 @@ __host__ __device__ inline int64_t block_level(double crit, int64_t dt_old, int6
     if (q < dt_old) return q;
     if (q > dt_old && (dt_old << 1) <= dmax && (t_new % (dt_old << 1)) == 0) return dt_old << 1;
     return dt_old;
+}
+
+__device__ __forceinline__ double norm3(double a, double b, double c) { return sqrt(a * a + b * b + c * c); }
+
+// Corrector for the active block (Makino & Aarseth 1992 Hermite scheme):
+// with D = dt_i, the predicted state recomputed exactly as in the pack,
+//   a2 = (-6 (a0 - a1) - D (4 j0 + 2 j1)) / D^2
+//   a3 = (12 (a0 - a1) + 6 D (j0 + j1)) / D^3
+//   x1 = x_p + a2 D^4/24 + a3 D^5/120,  v1 = v_p + a2 D^3/6 + a3 D^4/24,
+// then the Aarseth criterion with a2 carried to the new time, and the
+// power-of-two level rule.
+__device__ __forceinline__ void correct_core(const CorrectArgs& a, int c, const double* a1in,
+                                             const double* j1in) {
+    const int i = a.idx ? a.idx[c] : c;
+    const int64_t tn = a.tnext ? *a.tnext : a.tn;
+    if (c == 0 && a.tnow) *a.tnow = tn;
+    const double D = (double)a.dt[i] * kTick;
+    double* X[3] = {a.x, a.y, a.z};
+    double* V[3] = {a.vx, a.vy, a.vz};
+    double* A[3] = {a.ax, a.ay, a.az};
+    double* J[3] = {a.jx, a.jy, a.jz};
+    const double Dp = (double)(tn - a.t[i]) * kTick;   // equals D for an active particle
+    double a1[3], j1[3], a2[3], a3[3];
+    const double iD = 1.0 / D, iD2 = iD * iD, iD3 = iD2 * iD;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        double xp, vp;
+        predict1(X[k][i], V[k][i], A[k][i], J[k][i], Dp, xp, vp);
+        a1[k] = a1in[k];
+        j1[k] = j1in[k];
+        const double a0 = A[k][i], j0 = J[k][i];
+        const double da = a0 - a1[k];
+        a2[k] = (-6.0 * da - D * (4.0 * j0 + 2.0 * j1[k])) * iD2;
+        a3[k] = (12.0 * da + 6.0 * D * (j0 + j1[k])) * iD3;
+        const double D2 = D * D, D3 = D2 * D, D4 = D3 * D;
+        X[k][i] = xp + D4 * (a2[k] * (1.0 / 24.0) + D * a3[k] * (1.0 / 120.0));
+        V[k][i] = vp + D3 * (a2[k] * (1.0 / 6.0) + D * a3[k] * (1.0 / 24.0));
+        A[k][i] = a1[k];
+        J[k][i] = j1[k];
+    }
+    a.t[i] = tn;
+    if (a.pack_next) {
+        // the next shared step's record of this particle, from the state just
+        // written (read back through memory, as a pack pass reads it)
+        PackArgs p{};
+        p.x = a.x; p.y = a.y; p.z = a.z;
+        p.vx = a.vx; p.vy = a.vy; p.vz = a.vz;
+        p.m = a.m;
+        p.ax = a.ax; p.ay = a.ay; p.az = a.az;
+        p.jx = a.jx; p.jy = a.jy; p.jz = a.jz;
+        p.t = a.t;
+        p.out = a.pack_next;
+        if (a.pack_prec == 1)
+            pack_one<1>(p, i, a.tn_next);
+        else
+            pack_one<0>(p, i, a.tn_next);
+    }
+    if (!a.shared) {
+        const double b0 = a2[0] + a3[0] * D, b1 = a2[1] + a3[1] * D, b2 = a2[2] + a3[2] * D;
+        const double na = norm3(a1[0], a1[1], a1[2]), nj = norm3(j1[0], j1[1], j1[2]);
+        const double n2 = norm3(b0, b1, b2), n3 = norm3(a3[0], a3[1], a3[2]);
+        const double crit = sqrt(a.eta * (na * n2 + nj * nj) / (nj * n3 + n2 * n2));
+        const int64_t dtn = block_level(crit, a.dt[i], tn, a.lmin, a.lmax);
+        a.dt[i] = dtn;
+        // the next block time of this particle joins its chunk's minimum
+        // (ticks are non-negative, so the unsigned minimum is the minimum)
+        if (a.gmin_next)
+            atomicMin((unsigned long long*)&a.gmin_next[i / a.gch], (unsigned long long)(tn + dtn));
+    }
+}
+
+
+__device__ __forceinline__ void correct_one(const CorrectArgs& a, int c) {
+    double a1[3], j1[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        a1[k] = a.f[k][c];
+        j1[k] = a.f[3 + k][c];
+    }
+    correct_core(a, c, a1, j1);
 }
 
 }  // namespace nb

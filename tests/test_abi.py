@@ -120,6 +120,44 @@ def test_force_acc_nn_leapfrog_argument_errors(hostctx):
     assert lf(n=0, x=None) == -4              # nothing to move: reaches the device check
 
 
+@pytest.mark.timeout(60)
+def test_reserve_sizing_terminates(hostctx):
+    """nbody_reserve sizes the split partials on the host (before it needs a
+    device) over max_i and the powers of two below it; the walk must end for
+    every max_i, powers of two included (a host context then reports the
+    missing device)."""
+    L = nb.lib()
+    h = hostctx.handle
+    for ni in (0, 1, 2, 3, 4, 1000, 3000, 4096, 65536, 1 << 20, (1 << 31) - 1):
+        assert L.nbody_reserve(h, ni, 4096) == -4, ni
+
+
+def test_force_tile_environment_override(monkeypatch):
+    """NBODY_FORCE_TILE pins the launch shape of every precision that
+    compiles it (read at nbody_create, before any device work); a shape no
+    precision has makes nbody_create fail with NBODY_ERR_ARG."""
+    monkeypatch.setenv("NBODY_FORCE_TILE", "256,2,256,0,0,101")
+    c = nb.Context(-1)
+    try:
+        for prec in ("ds", "fp32"):
+            t = c.get_tile(1 << 20, 1 << 20, prec)
+            assert (t["tile_j"], t["ipt"], t["wg"], t["unroll"]) == (256, 2, 256, 101), (prec, t)
+    finally:
+        c.close()
+    monkeypatch.setenv("NBODY_FORCE_TILE", "64,1,128,3")
+    c = nb.Context(-1)
+    try:
+        t = c.get_tile(5000, 5000, "ds")
+        assert (t["tile_j"], t["ipt"], t["wg"], t["split"]) == (64, 1, 128, 3)
+    finally:
+        c.close()
+    for bad in ("100,2,256", "256,3,256", "nonsense", "64,1,128,-1"):
+        monkeypatch.setenv("NBODY_FORCE_TILE", bad)
+        with pytest.raises(nb.NBodyError) as e:
+            nb.Context(-1)
+        assert e.value.code == -1, bad
+
+
 def test_other_entry_points_validate(hostctx):
     L = nb.lib()
     h = hostctx.handle

@@ -378,7 +378,16 @@ def test_heavy_particles_potential_every_path(ctx, prec):
     tile loop that masks the self pair: launch shapes with one, two and
     four i per lane, split and unsplit, the scalar-cache j path, an i-subset
     given by i_self, the force-only and the nearest-neighbour evaluations,
-    and the batched kernel."""
+    and the batched kernel.
+
+    The DS bar on the heavy particles' potential is 4e-6.  Here the other
+    heavy particles (m = 1) share each 256-record float32 tile sum with
+    light ones (m = 1e-6), so the light terms are added at the rounding
+    scale of the heavy ones: a float32 emulation of the DS arithmetic (exact
+    rsq, 256-record tiles, two-sum folds between tiles) gives 1.64e-6 on this
+    set (7.4e-7 with 128-record tiles).  A self term left in the tile sum
+    and removed afterwards in float64 (Section 3.1's order) gives 1.4e-3 in
+    the same emulation: the bar separates the two by three orders."""
     import torch
     x, v, m = _heavy_set()
     n = m.size
@@ -386,7 +395,7 @@ def test_heavy_particles_potential_every_path(ctx, prec):
     heavy = np.flatnonzero(m == 1.0)
     ref = oracle.force(x, v, x, v, m, eps, iself=np.arange(n))
     assert (m[heavy] / eps / np.abs(ref[2][heavy])).min() > 1e3
-    bar = 1e-6 if prec == "ds" else 1e-4
+    bar = 4e-6 if prec == "ds" else 1e-4
     X, V, M = dev(x), dev(v), dev(m)
     S = torch.arange(n, dtype=torch.int32, device="cuda")
 

@@ -407,3 +407,89 @@ def test_salpeter64k_energy_drift_per_time_unit(ctx):
         assert t1 == 1.0
         assert abs(de) / t1 < 1e-6, (prec, de)
         h.close()
+
+
+@pytest.mark.parametrize("prec", ["ds", "fp32"])
+@pytest.mark.parametrize("levels", [(-20, -3), (-8, -8)])
+def test_block_step_forces_per_step(ctx, prec, levels):
+    """Block steps of the Salpeter recipe at N = 4096 (eps = 1e-3): after every
+    step, the new acceleration and jerk of the block's particles (the
+    pairwise sums of the step, reduced over the j-ranges) against the
+    oracle's forces on the same predicted state, particle by particle.  The
+    state before the step is read back, every particle is predicted to the
+    block time by the oracle's predictor, and the oracle evaluates the block
+    against all of them; so the check does not depend on the GPU and oracle
+    trajectories staying in lockstep (their step criteria are differences of
+    nearly equal accelerations and part within a few dozen steps).  The
+    block list and time are checked against the oracle's selection on the
+    same ticks.  Levels 2^-20..2^-3 give blocks of every size below 2048
+    (the j-parallel launch shape: single particles, partial groups) and a few
+    larger; one level 2^-8 makes every block the whole set (LDS tiles)."""
+    from gpu_util import BARS, rel_err_stats
+    p = ics.plummer(4096, 4711, "salpeter")
+    eps = 1e-3
+    lmin, lmax = levels
+    h = ctx.hermite(p.n, eps=eps, eta=0.02, dt_min_log2=lmin, dt_max_log2=lmax, prec=prec)
+    h.set_state(dev(p.pos), dev(p.vel), dev(p.mass))
+    bar_a, bar_j = BARS[prec]["acc"], BARS[prec]["jerk"]
+    sizes, worst = [], [0.0, 0.0]
+    s = gpu_state(h)
+    for k in range(100 if lmin < lmax else 6):
+        idx, tn = oracle.select_active(s["t"], s["dt"])
+        D = (tn - s["t"]) / TICKS
+        xp, vp = np.empty((3, p.n)), np.empty((3, p.n))
+        for q in range(p.n):
+            xp[:, q], vp[:, q] = oracle.predict(s["x"][:, q], s["v"][:, q], s["a"][:, q], s["jerk"][:, q], D[q])
+        ra, rj, _ = oracle.force(xp[:, idx], vp[:, idx], xp, vp, s["m"], eps, iself=idx)
+        na, tt = h.step()
+        assert (na, tt) == (idx.size, tn), k
+        s = gpu_state(h)
+        ea = rel_err_stats(s["a"][:, idx], ra)
+        ej = rel_err_stats(s["jerk"][:, idx], rj)
+        assert np.array_equal(s["t"][idx], np.full(idx.size, tn))
+        worst = [max(worst[0], ea["p99"]), max(worst[1], ej["p99"])]
+        assert ea["p99"] <= bar_a and ej["p99"] <= bar_j, (k, na, ea, ej)
+        sizes.append(na)
+    print(prec, levels, "blocks", len(sizes), "sizes min/median/max", min(sizes), int(np.median(sizes)),
+          max(sizes), "worst acc p99 %.2e jerk p99 %.2e" % tuple(worst), flush=True)
+    if lmin < lmax:
+        assert min(sizes) == 1 and any(1 < z < 2048 and z % 2 for z in sizes)
+    else:
+        assert min(sizes) == p.n
+
+
+def test_trace_lines_match_statistics(tmp_path, monkeypatch):
+    """NBODY_TRACE=<path>: one JSON line per step, block and shared; the
+    block lines' count, active sum and times agree with the integrator's own
+    statistics and with the oracle's block selection at the first step."""
+    import json
+    import paper_0707_0438_amd as nb
+    path = tmp_path / "trace.jsonl"
+    monkeypatch.setenv("NBODY_TRACE", str(path))
+    c = nb.Context(0)
+    monkeypatch.delenv("NBODY_TRACE")
+    try:
+        p = ics.plummer(3000, 4712, "salpeter")
+        h = c.hermite(p.n, eps=1e-3, eta=0.02, prec="ds")
+        h.set_state(dev(p.pos), dev(p.vel), dev(p.mass))
+        s0 = gpu_state(h)
+        idx0, tn0 = oracle.select_active(s0["t"], s0["dt"])
+        st = h.advance(TICKS // 128)
+        h.close()
+        hs = c.hermite(1024, eps=1.0 / 256, shared_dt_log2=-8, prec="fp32")
+        q = ics.workload("plummer1k_hermite")
+        hs.set_state(dev(q.pos), dev(q.vel), dev(q.mass))
+        hs.advance(3 * 4096)
+        hs.close()
+    finally:
+        c.close()
+    lines = [json.loads(ln) for ln in open(path)]
+    blk = [r for r in lines if r["mode"] == "block"]
+    sh = [r for r in lines if r["mode"] == "shared"]
+    assert len(blk) == st["steps"] and [r["step"] for r in blk] == list(range(1, st["steps"] + 1))
+    assert sum(r["n_act"] for r in blk) == st["sum_active"]
+    assert blk[0]["t_ticks"] == tn0 and blk[0]["n_act"] == idx0.size
+    t = [r["t_ticks"] for r in blk]
+    assert all(b > a for a, b in zip(t, t[1:])) and t[-1] <= TICKS // 128
+    assert all(r["shape"] in ("small", "large") and r["ranges"] >= 1 and r["groups"] >= 1 for r in blk)
+    assert [r["t_ticks"] for r in sh] == [4096, 8192, 12288] and all(r["n_act"] == 1024 for r in sh)
