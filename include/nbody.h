@@ -196,6 +196,28 @@ int nbody_force(nbody_ctx *ctx, hipStream_t stream, nbody_prec prec, double G, d
                 int64_t n_i, nbody_src I, const int32_t *i_self,
                 int64_t n_j, nbody_src J, nbody_out out);
 
+/* nbody_force without any device allocation, for callers that cannot
+ * allocate: code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc.  Same arguments, outputs and errors as nbody_force.
+ * Its packed particle records and split partial sums live in one 64 MiB
+ * array of device memory per GPU that the library holds from its first
+ * context on that device until the process ends; the call allocates and
+ * frees nothing (no hipMalloc, hipFree, events or library allocations).
+ * Limit: the packed records, 48 bytes per particle (DS) or 32 (FP32), for
+ * the j set plus the i set (the i set only when it is not the j set itself)
+ * must fit in 64 MiB, else NBODY_ERR_ARG with the sizes in
+ * nbody_last_error.  When the split partial sums (56 bytes per i and
+ * j-range) of the launch shape nbody_force would use do not fit in the
+ * rest, fewer j-ranges are used; the results then differ from
+ * nbody_force's in rounding only.  Every call on one GPU uses that GPU's
+ * array, across all contexts: two calls that overlap in time on one GPU
+ * (different streams, threads or contexts) race and give wrong results.
+ * Nothing in the array needs to start at zero.  NBODY_DEBUG_SELF_CHECK and
+ * kernel timing do not apply to this call. */
+int nbody_force_noalloc(nbody_ctx *ctx, hipStream_t stream, nbody_prec prec, double G, double eps,
+                        int64_t n_i, nbody_src I, const int32_t *i_self,
+                        int64_t n_j, nbody_src J, nbody_out out);
+
 /* Force-only evaluation: acceleration and potential as in nbody_force,
  * without the jerk.  Section 4 runs the library under a treecode, which
  * integrates with the acceleration alone, with the jerk and nearest-neighbour

@@ -35,6 +35,7 @@ EXPORTS = [
     "nbody_kernel_time", "nbody_force_vjp", "nbody_force_vjp_self", "nbody_shared_ckpt_bytes",
     "nbody_shared_run", "nbody_shared_adjoint", "nbody_force_batched", "nbody_batch_hermite",
     "nbody_autotune_batched", "nbody_force_acc", "nbody_force_nn", "nbody_leapfrog",
+    "nbody_force_noalloc",
 ]
 
 #: The GRAPE-6-style interface (include/nbody_grape.h).
@@ -111,6 +112,7 @@ def lib():
         "nbody_autotune": ([P, P, I, D, D, I64, Src, I64, Src, Out, I, C.POINTER(Tile),
                             C.POINTER(D)], I),
         "nbody_force": ([P, P, I, D, D, I64, Src, P, I64, Src, Out], I),
+        "nbody_force_noalloc": ([P, P, I, D, D, I64, Src, P, I64, Src, Out], I),
         "nbody_select_active": ([P, P, I64, P, P, P, C.POINTER(I64), C.POINTER(I64)], I),
         "nbody_hermite_create": ([P, C.POINTER(P), I64, C.POINTER(HermiteOpts)], I),
         "nbody_hermite_destroy": ([P], I),
@@ -279,9 +281,11 @@ class Context:
         return t.as_dict()
 
     def force(self, xi, vi, xj, vj, mj, eps, G=1.0, prec="ds", i_self=None, out=None,
-              stream=None):
+              stream=None, noalloc=False):
         """(acc (3, n_i), jerk (3, n_i), pot (n_i,)) of i due to j; see
-        nbody_force.  ``i_self`` is an int32 tensor (n_i,) or None."""
+        nbody_force.  ``i_self`` is an int32 tensor (n_i,) or None.
+        ``noalloc``: call nbody_force_noalloc instead (no device allocation
+        inside the library; pass ``out`` to allocate nothing at all)."""
         torch = _torch()
         ni, nj = xi.shape[1], xj.shape[1]
         I = _src(xi, vi, None, ni, "I")
@@ -295,8 +299,10 @@ class Context:
         a, j = _rows(acc, ni, "acc"), _rows(jerk, ni, "jerk")
         O = Out(a[0], a[1], a[2], j[0], j[1], j[2], _vec(pot, ni, "pot"))
         sp = _vec(i_self, ni, "i_self", torch.int32) if i_self is not None else None
-        self._check(lib().nbody_force(self._h, _stream(stream), PREC[prec], float(G), float(eps),
-                                      ni, I, sp, nj, J, O), "nbody_force")
+        fn, name = ((lib().nbody_force_noalloc, "nbody_force_noalloc") if noalloc
+                    else (lib().nbody_force, "nbody_force"))
+        self._check(fn(self._h, _stream(stream), PREC[prec], float(G), float(eps), ni, I, sp, nj, J, O),
+                    name)
         return acc, jerk, pot
 
     def force_acc(self, xi, xj, mj, eps, G=1.0, prec="ds", i_self=None, stream=None):

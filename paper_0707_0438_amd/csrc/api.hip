@@ -9,6 +9,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -29,6 +30,54 @@ struct DevBuf {
     size_t bytes = 0;
 };
 
+// Caller-provided room for the split partial sums (the allocation-free
+// entry point): run_force takes its partials from here, never allocates,
+// and uses fewer j-ranges when the shape's partials would not fit.
+struct FixedWS {
+    float2* part = nullptr;
+    size_t bytes = 0;
+};
+
+}  // namespace
+
+// Device memory of the allocation-free evaluation (nbody_force_noalloc): one
+// array per GPU, loaded with the library's code object and held until the
+// process ends.  In host code `scratch` names a host-side stand-in, not a
+// device address: the address on each device comes from
+// hipGetSymbolAddress, taken once per device at context creation
+// (scratch_setup) and kept in g_scratch.
+constexpr size_t kNoAllocBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch[kMaxDevices] = {};         // device address of `scratch` per device
+hipError_t g_scratch_err[kMaxDevices] = {}; // result of the lookup (hipSuccess once found)
+bool g_scratch_tried[kMaxDevices] = {};
+
+// With `device` current: look up its copy of `scratch` once.
+void scratch_setup(int device) {
+    if (device < 0 || device >= kMaxDevices) return;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_tried[device] && g_scratch_err[device] == hipSuccess) return;
+    void* ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    g_scratch_tried[device] = true;
+    g_scratch_err[device] = e;
+    g_scratch[device] = e == hipSuccess ? ptr : nullptr;
+    if (e != hipSuccess) (void)hipGetLastError();
+}
+
+void* scratch_ptr(int device, hipError_t* err) {
+    if (device < 0 || device >= kMaxDevices) {
+        *err = hipErrorInvalidDevice;
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    *err = g_scratch_tried[device] ? g_scratch_err[device] : hipErrorNotInitialized;
+    return g_scratch[device];
+}
 }  // namespace
 
 struct nbody_ctx {
@@ -244,8 +293,9 @@ static int run_force(nbody_ctx* c, hipStream_t st, int prec, double G, double ep
                      const float4* ipack, const int32_t* iidx, const int32_t* iself, int self_mode,
                      int64_t nj, const float4* jpack, double* const out[7], const nbody_tile* forced,
                      int kind = 0, int32_t* nn = nullptr, double* nn_r2 = nullptr,
-                     int* defer_split = nullptr) {
+                     int* defer_split = nullptr, const FixedWS* fixed = nullptr) {
     if (ni == 0) return NBODY_OK;
+    if (fixed && (kind != 0 || defer_split)) return set_err(c, NBODY_ERR_ARG, "fixed workspace needs kind 0");
     if (defer_split && kind != 0) return set_err(c, NBODY_ERR_ARG, "deferred split reduce needs kind 0");
     nbody_tile t;
     if (forced) {
@@ -279,6 +329,11 @@ static int run_force(nbody_ctx* c, hipStream_t st, int prec, double G, double ep
     }
     int nb, S, jchunk;
     split_plan(ni, nj, wg * ipt, tj, t.split, &nb, &S, &jchunk);
+    if (fixed && S > 1) {
+        // as many j-ranges as the fixed workspace holds partials for
+        const int64_t fit = (int64_t)(fixed->bytes / (sizeof(float2) * 7 * (size_t)ni));
+        if (fit < S) split_plan(ni, nj, wg * ipt, tj, (int)std::max<int64_t>(fit, 1), &nb, &S, &jchunk);
+    }
 
     ForceArgs a{};
     a.ipack = ipack;
@@ -298,13 +353,19 @@ static int run_force(nbody_ctx* c, hipStream_t st, int prec, double G, double ep
     a.partial = S > 1 ? 1 : 0;
     if (S > 1) {
         const size_t rows = kind == 2 ? 8 : 7;
-        int rc = dev_alloc(c, c->part, sizeof(float2) * rows * (size_t)S * (size_t)ni);
-        if (rc) return rc;
-        a.part = (float2*)c->part.p;
+        const size_t need = sizeof(float2) * rows * (size_t)S * (size_t)ni;
+        if (fixed) {
+            if (need > fixed->bytes) return set_err(c, NBODY_ERR_ARG, "split partials exceed the fixed workspace");
+            a.part = fixed->part;
+        } else {
+            int rc = dev_alloc(c, c->part, need);
+            if (rc) return rc;
+            a.part = (float2*)c->part.p;
+        }
         if (kind == 2) a.nnpart = a.part + 7 * (size_t)S * (size_t)ni;
     }
     hipEvent_t tb = nullptr, te = nullptr;
-    if (c->timing) {
+    if (c->timing && !fixed) {
         while (c->ev.size() < c->ev_used + 2) {
             hipEvent_t x;
             if (hipEventCreate(&x) != hipSuccess) return set_err(c, NBODY_ERR_DEVICE, "event create");
@@ -433,6 +494,8 @@ int nbody_create(nbody_ctx** ctx, int device, const char* tune_cache_path) {
         }
         c->tune.set_arch(prop.gcnArchName);
         c->tune.load();
+        DeviceGuard g(device);
+        if (g.ok) scratch_setup(device);
     }
     c->device = device;
     *ctx = c;
@@ -606,6 +669,50 @@ int nbody_force(nbody_ctx* c, hipStream_t st, nbody_prec prec, double G, double 
     double* o[7] = {out.ax, out.ay, out.az, out.jx, out.jy, out.jz, out.pot};
     return run_force(c, st, p, G, eps, n_i, ip, nullptr, i_self, 0, n_j, (const float4*)c->jpack.p, o,
                      nullptr);
+}
+
+int nbody_force_noalloc(nbody_ctx* c, hipStream_t st, nbody_prec prec, double G, double eps, int64_t n_i,
+                        nbody_src I, const int32_t* i_self, int64_t n_j, nbody_src J, nbody_out out) {
+    if (!c) return NBODY_ERR_ARG;
+    if (int rc = check_common(c, prec, G, eps)) return rc;
+    if (n_i < 0 || n_j < 0) return set_err(c, NBODY_ERR_ARG, "n_i and n_j must be >= 0");
+    if (n_i > kMaxN || n_j > kMaxN) return set_err(c, NBODY_ERR_ARG, "n_i and n_j must be <= 2^31-1");
+    if (n_i > 0) {
+        if (int rc = check_src(c, I, false, "I")) return rc;
+        if (int rc = check_out(c, out)) return rc;
+    }
+    if (n_j > 0)
+        if (int rc = check_src(c, J, true, "J")) return rc;
+    if (n_i > 0 && n_j == 0 && i_self)
+        return set_err(c, NBODY_ERR_ARG, "i_self given with an empty j set");
+    if (int rc = need_device(c)) return rc;
+    const int p = (int)prec;
+    const bool own = n_i == n_j && same_src(I, J);
+    // packed records, each rounded up to 256 bytes, then the split partials
+    auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    const size_t rec = sizeof(float4) * (size_t)rec_words(p);
+    const size_t jb = up(rec * (size_t)n_j), ib = own ? 0 : up(rec * (size_t)n_i);
+    if (jb + ib > kNoAllocBytes)
+        return set_err(c, NBODY_ERR_ARG,
+                       "nbody_force_noalloc: %lld i and %lld j records need %zu bytes, beyond its %zu-byte scratch",
+                       (long long)n_i, (long long)n_j, jb + ib, kNoAllocBytes);
+    if (n_i == 0) return NBODY_OK;
+    DeviceGuard g(c->device);
+    if (!g.ok) return set_err(c, NBODY_ERR_DEVICE, "hipSetDevice(%d) failed", c->device);
+    hipError_t se;
+    unsigned char* base = (unsigned char*)scratch_ptr(c->device, &se);
+    if (!base) return hip_err(c, se, "nbody_force_noalloc: device address of the scratch array");
+    float4* jp = (float4*)base;
+    float4* ip = own ? jp : (float4*)(base + jb);
+    int rc = pack_into(c, st, p, n_j, J, true, jp);
+    if (!rc && !own) rc = pack_into(c, st, p, n_i, I, false, ip);
+    if (rc) return rc;
+    FixedWS ws;
+    ws.part = (float2*)(base + jb + ib);
+    ws.bytes = kNoAllocBytes - jb - ib;
+    double* o[7] = {out.ax, out.ay, out.az, out.jx, out.jy, out.jz, out.pot};
+    return run_force(c, st, p, G, eps, n_i, ip, nullptr, i_self, 0, n_j, jp, o, nullptr, 0, nullptr, nullptr,
+                     nullptr, &ws);
 }
 
 // Shared argument checks and packing of nbody_force_acc / nbody_force_nn.
