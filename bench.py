@@ -35,8 +35,10 @@ FP32_PEAK_TFLOPS = 157.3            # MI355X FP32 vector peak (256 CU x 64 x 2 x
 PAPER_GINT_S = 1.0995116e12 / 279.4067 / 1e9   # 8800GTX, N = 2^20, Table 4 (context)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "force_ds_plummer1m_traffic.txt")
 VALU_FILE = os.path.join(ROOT, "profiles", "force_plummer1m_valu_clock.txt")
-FORCE_SRC = os.path.join(ROOT, "paper_0707_0438_amd", "csrc", "force.hip")
-LAUNCH_SRC = os.path.join(ROOT, "paper_0707_0438_amd", "csrc", "api.hip")
+# the headline kernel: its tile loop, its instantiations and the rules that
+# pick its launch shape and j-split
+KERNEL_SRCS = [os.path.join(ROOT, "paper_0707_0438_amd", "csrc", f)
+               for f in ("force_block.h", "force.hip", "launch_shape.h")]
 
 
 def log(*a):
@@ -47,7 +49,7 @@ def kernel_source_sha256() -> str:
     """One sha256 over the pairwise kernels and the launch-shape rules they run
     under; counter summaries record it and are used only while it matches."""
     h = hashlib.sha256()
-    for src in (FORCE_SRC, LAUNCH_SRC):
+    for src in KERNEL_SRCS:
         h.update(open(src, "rb").read())
     return h.hexdigest()
 

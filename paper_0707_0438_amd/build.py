@@ -14,7 +14,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libnbody.so")
-SOURCES = ["force.hip", "pack.hip", "hermite.hip", "vjp.hip", "shared.hip", "leapfrog.hip", "api.hip", "grape.hip"]
+SOURCES = ["force.hip", "blockstep.hip", "pack.hip", "hermite.hip", "vjp.hip", "shared.hip", "leapfrog.hip",
+           "api.hip", "grape.hip"]
 ARCH = os.environ.get("NBODY_OFFLOAD_ARCH", "gfx950")
 
 

@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "nbody.h"
+#include "force_block.h"
 #include "nbody_internal.h"
 #include "tune.h"
 
@@ -213,66 +214,6 @@ static bool valid_tile(const nbody_tile& t) {
     if (t.split < 0 || t.split > 4096 || (t.jsrc != 0 && t.jsrc != 1)) return false;
     return force_variant_exists(0, t.ipt, t.tile_j, t.wg, t.jsrc, t.unroll, t.waves, false) ||
            force_variant_exists(1, t.ipt, t.tile_j, t.wg, t.jsrc, t.unroll, t.waves, false);
-}
-
-// Number of j-ranges for an i-list of ni against nj (see split_plan).  Long
-// evaluations also split j: with at least kLongWG work-groups in all, the
-// last, partly filled round of resident work-groups is a small part of the
-// launch.  Each range keeps at least kLongTiles tiles, and the partials stay
-// below (kLongWG + i-blocks) x (i per block) x 56 B.  On MI355X at N = 2^20
-// this took the large DS evaluation from 749 to 726 ms (4096 i-blocks, 8
-// ranges), and 2^17 i against 2^20 j from 96 to 90 ms (64 ranges).
-constexpr int64_t kLongWG = 32768;
-constexpr int64_t kLongTiles = 64;
-// The long-evaluation split keeps its partial sums (8 rows of 8 bytes per
-// i and range at most) within this many bytes.
-constexpr int64_t kLongPartBytes = (int64_t)1 << 31;
-static int choose_split(int64_t ni, int64_t nj, const nbody_tile& t) {
-    int nb, S, jc;
-    split_plan(ni, nj, t.wg * t.ipt, t.tile_j, 0, &nb, &S, &jc);
-    const int64_t per = (int64_t)t.wg * t.ipt;
-    const int64_t nbl = (ni + per - 1) / per;
-    int64_t Sl = nbl > 0 ? (kLongWG + nbl - 1) / nbl : 1;
-    Sl = std::min<int64_t>(Sl, nj / (kLongTiles * t.tile_j));
-    Sl = std::min<int64_t>(Sl, kLongPartBytes / (64 * std::max<int64_t>(ni, 1)));
-    return (int)std::max<int64_t>(S, Sl);
-}
-
-// Default launch shape when neither an override nor a tuned entry exists:
-// the fastest shape of the MI355X sweep at 2^20 x 2^20 (256-record LDS
-// tiles, software-pipelined LDS reads; two i per lane for DS, one for plain
-// FP32) for large problems,
-// 64-record tiles for small ones (more j-ranges to spread over the CUs), and
-// for the smallest j sets (latency-bound: the time is one work-group's
-// sweep) 32- or 16-record tiles in one-wave work-groups.  short_tiles: the
-// evaluation kind has those shapes.
-static nbody_tile default_tile(int prec, int64_t ni, int64_t nj, bool short_tiles = true) {
-    nbody_tile t;
-    const bool large = (double)ni * (double)nj >= 4294967296.0;
-    t.tile_j = large ? 256 : 64;
-    t.wg = large ? 256 : 128;
-    if (!large && short_tiles && nj <= 2048) {
-        t.tile_j = nj <= 512 ? 16 : 32;
-        t.wg = 64;
-    }
-    // DS at large sizes: two i per lane (with the long-evaluation split,
-    // 683 ms at 2^20 against 709-713 ms for one i per lane, same box);
-    // plain FP32 keeps one i per lane (578-580 ms against 594)
-    t.ipt = (large && prec == 1) ? 2 : 1;
-    t.split = 0;
-    t.jsrc = 0;
-    t.unroll = large ? (prec == 1 ? 101 : 102) : 0;
-    t.waves = 0;
-    return t;
-}
-
-// Defaults of the force-only (kind 1) and nearest-neighbour (kind 2)
-// evaluations: the fastest shapes of the MI355X sweep at 2^20 x 2^20; small
-// problems take the small default shape.
-static nbody_tile default_tile_kind(int kind, int prec, int64_t ni, int64_t nj) {
-    // the full evaluation's default (two i per lane for DS at large sizes) is
-    // also the fastest force-only and neighbour shape of the sweeps
-    return default_tile(prec, ni, nj, kind == 0);
 }
 
 static nbody_tile pick_tile(nbody_ctx* c, int prec, int64_t ni, int64_t nj) {
@@ -1201,7 +1142,7 @@ static int hermite_enqueue_block(nbody_hermite* h, hipStream_t st) {
     for (int q = 0; q < 7; ++q) a.out[q] = h->f[q];
     a.part = (float2*)c->part.p;
     a.plan = h->plan;
-#if NB_BLK_STEP_FUSED
+#if NB_BLK_STEP_FUSED == 1
     {
         CorrectArgs ca = correct_args(h, n);
         ca.gmin_next = gmin_next;
@@ -1212,8 +1153,11 @@ static int hermite_enqueue_block(nbody_hermite* h, hipStream_t st) {
         h->gmin_ok = true;
         return NBODY_OK;
     }
-#endif
+#elif NB_BLK_STEP_FUSED == 2
+    e = launch_blk_step(p, eps0, a, CorrectArgs{}, nullptr, st);
+#else
     e = launch_force_plan(p, eps0, a, st);
+#endif
     if (e != hipSuccess) return hip_err(c, e, "force launch");
     ReduceArgs r{};
     r.ni = n;

@@ -1,0 +1,285 @@
+// Block steps after the front end in one or two launches (Section 3.1's
+// block step, with the prediction and selection already done on the
+// device): the pairwise sums of the plan's block for either launch shape,
+// and optionally the split reduce and the corrector.
+#include "force_block.h"
+
+namespace nb {
+
+// ---- block steps: pairwise sums, split reduce and corrector in one launch ----
+//
+// Small blocks (the plan's shape 0) are j-parallel: the kJparIG i-particles
+// of a group are the same in every lane (uniform loads), and lane l of the
+// work-group takes the j records jb + l + 256 k (k < kJparJPL) of its range,
+// so that no lane idles however few particles are due.  Each lane adds its
+// few pairs in float32; the 256 lane sums of each quantity are then added in
+// float64 in a fixed order and stored as the range's (hi, lo) partial.
+// Large blocks (shape 1) keep the tile loop of the large direct
+// evaluations: one i per lane, 256-record LDS tiles, software-pipelined
+// reads.  The self pair needs no mask here: an i record is its own j record,
+// so its separation and relative velocity are exactly zero and it adds
+// exactly nothing to the acceleration and jerk (the potential is not formed).
+template <int PREC, bool EPS0>
+__device__ __forceinline__ void jpar_block(const ForceArgs& a, int n_act, int g, int s, int jb, int je,
+                                           float* smem) {
+    constexpr int R = Rec<PREC>::R;
+    constexpr int IG = kJparIG, JPL = kJparJPL, WG = kBlkStepWG;
+    float* red = smem;                  // [IG * 6][WG]: high words of the lane sums
+    float* losh = smem + IG * 6 * WG;   // [IG * 6][WG]: their low words
+    const int tid = threadIdx.x;
+    float ix[IG], iy[IG], iz[IG], iu[IG], iv[IG], iw[IG], lx[IG], ly[IG], lz[IG];
+#pragma unroll
+    for (int k = 0; k < IG; ++k) {
+        const int c = g * IG + k;
+        float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f), r1 = r0, r2 = r0;
+        if (c < n_act) {
+            const int src = a.iidx[c];
+            r0 = a.ipack[(size_t)src * R + 0];
+            r1 = a.ipack[(size_t)src * R + 1];
+            if (PREC == 1) r2 = a.ipack[(size_t)src * R + 2];
+        }
+        ix[k] = r0.x; iy[k] = r0.y; iz[k] = r0.z;
+        iu[k] = r1.x; iv[k] = r1.y; iw[k] = r1.z;
+        lx[k] = r2.x; ly[k] = r2.y; lz[k] = r2.z;
+    }
+    float eps2v;
+    asm volatile("v_mov_b32 %0, %1" : "=v"(eps2v) : "s"(a.eps2));
+    float hi[IG][6];
+#pragma unroll
+    for (int k = 0; k < IG; ++k)
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+            hi[k][q] = 0.f;
+            losh[(k * 6 + q) * WG + tid] = 0.f;
+        }
+    // sweeps of WG x JPL records: lane l takes j0 + l + WG u (u < JPL), all
+    // loads first; each sweep's float32 sums fold into a two-sum per lane
+    for (int j0 = jb; j0 < je; j0 += WG * JPL) {
+        float4 q0[JPL], q1[JPL], q2[JPL];
+#pragma unroll
+        for (int u = 0; u < JPL; ++u) {
+            const int j = j0 + tid + WG * u;
+            q0[u] = make_float4(kPadPos, kPadPos, kPadPos, 0.f);
+            q1[u] = make_float4(0.f, 0.f, 0.f, 0.f);
+            q2[u] = q1[u];
+            if (j < je) {
+                q0[u] = a.jpack[(size_t)j * R + 0];
+                q1[u] = a.jpack[(size_t)j * R + 1];
+                if (PREC == 1) q2[u] = a.jpack[(size_t)j * R + 2];
+            }
+        }
+        float acc[IG][6];
+#pragma unroll
+        for (int k = 0; k < IG; ++k)
+#pragma unroll
+            for (int q = 0; q < 6; ++q) acc[k][q] = 0.f;
+#pragma unroll
+        for (int u = 0; u < JPL; ++u) {
+#pragma unroll
+            for (int k = 0; k < IG; ++k) {
+                float dx, dy, dz;
+                if (PREC == 1) {
+                    dx = (q0[u].x - ix[k]) + (q2[u].x - lx[k]);
+                    dy = (q0[u].y - iy[k]) + (q2[u].y - ly[k]);
+                    dz = (q0[u].z - iz[k]) + (q2[u].z - lz[k]);
+                } else {
+                    dx = q0[u].x - ix[k];
+                    dy = q0[u].y - iy[k];
+                    dz = q0[u].z - iz[k];
+                }
+                const float sq = fmaf(dz, dz, fmaf(dy, dy, fmaf(dx, dx, eps2v)));
+                float rinv = __builtin_amdgcn_rsqf(sq);
+                if (EPS0) rinv = sq > 0.f ? rinv : 0.f;
+                const float ux = q1[u].x - iu[k], uy = q1[u].y - iv[k], uz = q1[u].z - iw[k];
+                const float rv = fmaf(dz, uz, fmaf(dy, uy, dx * ux));
+                const float rinv2 = rinv * rinv;
+                const float mr3 = (q0[u].w * rinv) * rinv2;
+                const float al = 3.0f * rv * rinv2;
+                acc[k][0] = fmaf(mr3, dx, acc[k][0]);
+                acc[k][1] = fmaf(mr3, dy, acc[k][1]);
+                acc[k][2] = fmaf(mr3, dz, acc[k][2]);
+                acc[k][3] = fmaf(mr3, fmaf(-al, dx, ux), acc[k][3]);
+                acc[k][4] = fmaf(mr3, fmaf(-al, dy, uy), acc[k][4]);
+                acc[k][5] = fmaf(mr3, fmaf(-al, dz, uz), acc[k][5]);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < IG; ++k)
+#pragma unroll
+            for (int q = 0; q < 6; ++q) {
+                float lo = losh[(k * 6 + q) * WG + tid];
+                two_sum_fold(hi[k][q], lo, acc[k][q]);
+                losh[(k * 6 + q) * WG + tid] = lo;
+            }
+    }
+    // lane sums -> LDS; then 8 threads per (i, quantity) add 32 lanes each in
+    // float64, in lane order (high then low word), and a fixed butterfly
+    // joins the 8
+#pragma unroll
+    for (int k = 0; k < IG; ++k)
+#pragma unroll
+        for (int q = 0; q < 6; ++q) red[(k * 6 + q) * WG + tid] = hi[k][q];
+    __syncthreads();
+    if (tid < IG * 6 * 8) {
+        const int cq = tid >> 3, part = tid & 7;
+        const int l0 = cq * WG + part * (WG / 8);
+        double f = 0.0;
+#pragma unroll 8
+        for (int l = 0; l < WG / 8; ++l) {
+            f += (double)red[l0 + l];
+            f += (double)losh[l0 + l];
+        }
+        f += __shfl_xor(f, 1);
+        f += __shfl_xor(f, 2);
+        f += __shfl_xor(f, 4);
+        const int k = cq / 6, q = cq - 6 * (cq / 6);
+        const int c = g * IG + k;
+        if (part == 0 && c < n_act) {
+            if (a.partial) {
+                const float h = (float)f;
+                a.part[((size_t)s * 7 + q) * n_act + c] = make_float2(h, (float)(f - (double)h));
+            } else {
+                // (a select chain: a runtime index into the by-value array
+                // of row pointers would place it in scratch memory)
+                double* o = q == 0 ? a.out[0] : q == 1 ? a.out[1] : q == 2 ? a.out[2]
+                          : q == 3 ? a.out[3] : q == 4 ? a.out[4] : a.out[5];
+                o[c] = a.G * f;
+            }
+        }
+    }
+}
+
+// LASTWG false: the pairwise sums only (partials, or the final forces when
+// the plan has one range); the split reduce and the corrector follow in
+// blk_reduce_correct_kernel.
+template <int PREC, bool EPS0, bool LASTWG>
+__global__ __launch_bounds__(kBlkStepWG) __attribute__((amdgpu_waves_per_eu(kBlkStepWaves)))
+void blk_step_kernel(ForceArgs a, CorrectArgs ca,
+                                                              unsigned* __restrict__ gcnt) {
+    constexpr int R = Rec<PREC>::R;
+    constexpr int kTileBytes = 2 * kBlkBigTile * R * (int)sizeof(float4);
+    constexpr int kRedBytes = 2 * kJparIG * 6 * kBlkStepWG * (int)sizeof(float);
+    __shared__ __align__(16) unsigned char smem[kTileBytes > kRedBytes ? kTileBytes : kRedBytes];
+    __shared__ double gsum[kJparIG * 6];
+    __shared__ int last_sh;
+    const DevPlan* pl = a.plan;
+    const int n = (int)pl->n_act;
+    if (n <= 0) return;
+    const int nb = pl->nb, S = pl->S, shape = pl->shape;
+    ForceArgs b = a;
+    b.ni = n;
+    b.jchunk = pl->jchunk;
+    b.partial = LASTWG || S > 1 ? 1 : 0;
+    const int tid = threadIdx.x;
+    for (int v = blockIdx.x; v < nb * S; v += gridDim.x) {
+        const int g = v % nb, s = v / nb;
+        const int jb = s * b.jchunk;
+        const int je = min(b.nj, jb + b.jchunk);
+        int gbeg, gend;
+        if (!EPS0 && shape == 1) {
+            force_block<PREC, 1, kBlkBigTile, kBlkStepWG, false, false, 2, true>(
+                b, reinterpret_cast<float4(*)[kBlkBigTile * R]>(smem), g * kBlkStepWG, n, jb, je, b.eps2, s);
+            gbeg = g * kBlkStepWG;
+            gend = min(n, gbeg + kBlkStepWG);
+        } else {
+            jpar_block<PREC, EPS0>(b, n, g, s, jb, je, reinterpret_cast<float*>(smem));
+            gbeg = g * kJparIG;
+            gend = min(n, gbeg + kJparIG);
+        }
+        if (!LASTWG) {
+            __syncthreads();   // LDS is rewritten by the next item
+            continue;
+        }
+        // This work-group's partial stores complete (work-group release and
+        // barrier), then one thread releases them device-wide (one L2
+        // write-back per work-group, no invalidation) and counts the range
+        // in.  The work-group that brings the count to S acquires (L1/L2
+        // invalidation, in that work-group only) and reads every range.
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __syncthreads();
+        if (tid == 0) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            last_sh = __hip_atomic_fetch_add(&gcnt[g], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ==
+                      (unsigned)(S - 1);
+        }
+        __syncthreads();
+        if (last_sh) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            const size_t qs = (size_t)n;
+            if (!EPS0 && shape == 1) {
+                // one thread per particle, ranges s = 0 .. S-1 in order
+                const int c = gbeg + tid;
+                if (c < gend) {
+                    double f[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+                    for (int sp = 0; sp < S; ++sp) {
+                        float2 u[6];
+#pragma unroll
+                        for (int q = 0; q < 6; ++q) u[q] = b.part[((size_t)sp * 7 + q) * qs + c];
+#pragma unroll
+                        for (int q = 0; q < 6; ++q) {
+                            f[q] += (double)u[q].x;
+                            f[q] += (double)u[q].y;
+                        }
+                    }
+#pragma unroll
+                    for (int q = 0; q < 6; ++q) f[q] *= b.G;
+                    correct_core(ca, c, f, f + 3);
+                }
+            } else {
+                // 8 threads per (particle, quantity): ranges s = part, part + 8,
+                // ... in order, then a fixed butterfly over the 8
+                if (tid < kJparIG * 6 * 8) {
+                    const int cq = tid >> 3, part = tid & 7;
+                    const int k = cq / 6, q = cq - 6 * (cq / 6);
+                    const int c = gbeg + k;
+                    double f = 0.0;
+                    if (c < gend)
+                        for (int sp = part; sp < S; sp += 8) {
+                            const float2 u = b.part[((size_t)sp * 7 + q) * qs + c];
+                            f += (double)u.x;
+                            f += (double)u.y;
+                        }
+                    f += __shfl_xor(f, 1);
+                    f += __shfl_xor(f, 2);
+                    f += __shfl_xor(f, 4);
+                    if (part == 0) gsum[cq] = b.G * f;
+                }
+                __syncthreads();
+                if (tid < kJparIG && gbeg + tid < gend) {
+                    const double* f = gsum + tid * 6;
+                    correct_core(ca, gbeg + tid, f, f + 3);
+                }
+            }
+            if (tid == 0) gcnt[g] = 0;   // ready for the next step
+        }
+        __syncthreads();   // LDS is rewritten by the next item
+    }
+}
+
+template <bool LASTWG>
+static void launch_blk_step_t(int prec, bool eps0, const ForceArgs& a, const CorrectArgs& ca, unsigned* gcnt,
+                              hipStream_t st) {
+    const dim3 g(kBlkGrid), b(kBlkStepWG);
+    if (prec == 0) {
+        if (eps0)
+            hipLaunchKernelGGL((blk_step_kernel<0, true, LASTWG>), g, b, 0, st, a, ca, gcnt);
+        else
+            hipLaunchKernelGGL((blk_step_kernel<0, false, LASTWG>), g, b, 0, st, a, ca, gcnt);
+    } else {
+        if (eps0)
+            hipLaunchKernelGGL((blk_step_kernel<1, true, LASTWG>), g, b, 0, st, a, ca, gcnt);
+        else
+            hipLaunchKernelGGL((blk_step_kernel<1, false, LASTWG>), g, b, 0, st, a, ca, gcnt);
+    }
+}
+
+hipError_t launch_blk_step(int prec, bool eps0, const ForceArgs& a, const CorrectArgs& ca, unsigned* gcnt,
+                           hipStream_t st) {
+    if (gcnt)
+        launch_blk_step_t<true>(prec, eps0, a, ca, gcnt, st);
+    else
+        launch_blk_step_t<false>(prec, eps0, a, ca, gcnt, st);
+    return hipGetLastError();
+}
+
+}  // namespace nb

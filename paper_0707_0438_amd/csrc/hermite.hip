@@ -255,7 +255,9 @@ __device__ __forceinline__ void blk_plan_write(DevPlan* plan, int64_t total, int
 #if NB_BLK_STEP_FUSED
     if (big) {
         split_plan(total, n, kBlkStepWG, kBlkBigTile, 0, &nb, &S, &jc, 1);
-        if (S > kBlkBigMaxS) split_plan(total, n, kBlkStepWG, kBlkBigTile, kBlkBigMaxS, &nb, &S, &jc, 1);
+        // the one-launch form reduces a group's ranges in one work-group
+        if (NB_BLK_STEP_FUSED == 1 && S > kBlkBigMaxS)
+            split_plan(total, n, kBlkStepWG, kBlkBigTile, kBlkBigMaxS, &nb, &S, &jc, 1);
     } else {
         // j-ranges: enough (group, range) items to spread over the device
         // (about kJparItems), at most kJparMaxS ranges and at least one
@@ -387,9 +389,11 @@ __global__ __launch_bounds__(kSelWG) void blk_write_plan_kernel(int n, int ch, i
 
 // The whole front end in one launch.  Work-group b owns chunk b: it takes
 // t_next from the kept chunk minima, counts its due particles, publishes
-// that count in pub[b] tagged with this step's number `tag` (release), then
-// predicts and packs its chunk, and only then waits for the counts of the
-// chunks before it (acquire) to place its part of the ordered block list.
+// that count in pub[b] tagged with this step's number `tag`, then predicts
+// and packs its chunk, and only then waits for the counts of the chunks
+// before it to place its part of the ordered block list.  The published
+// word is the only data passed between work-groups, so it is written and
+// polled with relaxed device-scope atomics (no fences).
 // Lower-numbered work-groups are dispatched first and never wait for higher
 // ones, so every wait ends; each wait is also bounded (kFrontSpin polls),
 // after which the plan records the failure (frozen = 2) and the step does
@@ -442,7 +446,9 @@ __global__ __launch_bounds__(kSelWG) void blk_front_kernel(int ch, int G, const 
     if (tid == 0) {
         gmin_next[b] = frozen ? gmin[b] : rest;
         if (b == 0) sel2[1] = tn;
-        __hip_atomic_store(&pub[b], ((uint64_t)tag << 32) | (uint32_t)c, __ATOMIC_RELEASE,
+        // relaxed: readers need this word's value only (no data written
+        // before it), so no release fence (an L2 write-back) is needed
+        __hip_atomic_store(&pub[b], ((uint64_t)tag << 32) | (uint32_t)c, __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
     }
     if (frozen) {
@@ -460,7 +466,8 @@ __global__ __launch_bounds__(kSelWG) void blk_front_kernel(int ch, int G, const 
         uint64_t v = 0;
         int it = 0;
         for (;;) {
-            v = __hip_atomic_load(&pub[g], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+            // relaxed (coherent at device scope, no L2 invalidation per poll)
+            v = __hip_atomic_load(&pub[g], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             if ((uint32_t)(v >> 32) == tag) break;
             if (++it >= kFrontSpin) {
                 fail_sh = 1;

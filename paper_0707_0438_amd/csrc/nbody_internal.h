@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "launch_shape.h"
+
 namespace nb {
 
 // One tick of integer time is 2^-20 N-body time units; block steps are
@@ -20,39 +22,6 @@ constexpr int kRecFP32 = 2;
 constexpr int kRecDS = 3;
 inline int rec_words(int prec) { return prec == 0 ? kRecFP32 : kRecDS; }
 
-// Launch geometry of the pairwise kernel for an i-list of ni against nj:
-// nb i-blocks of per_blk particles and S j-ranges of jchunk records (a
-// multiple of the tile).  Enough work-groups to cover the 256 CUs several
-// times, with at least min_tiles tiles per j-range.  Used by the host for direct
-// calls and by the device for block steps whose size only it knows.  Small
-// self-gravitating sets are latency-bound: a j-range of one tile per
-// work-group was the fastest on MI355X from N = 256 to 4096 (N = 1024:
-// pairwise 10.7 us against 28 us with four tiles per range).
-__host__ __device__ inline void split_plan(int64_t ni, int64_t nj, int per_blk, int tile_j, int split_req,
-                                           int* nb_out, int* S_out, int* jchunk_out, int min_tiles = 1) {
-    const int64_t nb = (ni + per_blk - 1) / per_blk;
-    int64_t S = split_req;
-    if (S <= 0) {
-        const int64_t target = 2048;
-        if (nb <= 0 || nb >= target / 2) {
-            S = 1;
-        } else {
-            S = (target + nb - 1) / nb;
-            int64_t smax = nj / ((int64_t)min_tiles * tile_j);
-            if (smax < 1) smax = 1;
-            if (S > smax) S = smax;
-            if (S < 1) S = 1;
-        }
-    }
-    int64_t jchunk = (nj + S - 1) / S;
-    jchunk = ((jchunk + tile_j - 1) / tile_j) * tile_j;
-    if (jchunk <= 0) jchunk = tile_j;
-    int64_t S2 = (nj + jchunk - 1) / jchunk;
-    if (S2 < 1) S2 = 1;
-    *nb_out = (int)nb;
-    *S_out = (int)S2;
-    *jchunk_out = (int)jchunk;
-}
 
 // One block step as the plan recorded it (NBODY_TRACE): written by the
 // device into a ring of kTraceCap records, read by the host at each chunk's
@@ -87,26 +56,31 @@ struct DevPlan {
 #define NB_BLK_SMALL_WG 128
 #endif
 #ifndef NB_BLK_BIG_MIN
-#define NB_BLK_BIG_MIN 2048
+#define NB_BLK_BIG_MIN 256
 #endif
 constexpr int kBlkSmallTile = NB_BLK_SMALL_TJ, kBlkSmallWG = NB_BLK_SMALL_WG;
 constexpr int kBlkBigTile = 256, kBlkBigWG = 256;
 constexpr int kBlkBigMin = NB_BLK_BIG_MIN;   // 0: the large shape is never used
 constexpr int kBlkGrid = 2048;               // work-groups of each plan-driven launch
-// 1: after the front end a block step is one launch (blk_step_kernel):
-// 256-lane work-groups; small blocks are j-parallel, in groups of kJparIG
+// Block-step launches after the front end.  0: the pairwise launches by
+// shape, then split reduce + corrector.  1: one launch (blk_step_kernel),
+// whose last work-group per i-group reduces that group's partials and runs
+// the corrector.  2: blk_step_kernel for the sums, then split reduce +
+// corrector.  In modes 1 and 2 the pairwise launch has 256-lane
+// work-groups; small blocks are j-parallel, in groups of kJparIG
 // i-particles against j-ranges swept 256 x kJparJPL records at a time;
-// large blocks take at most kBlkBigMaxS j-ranges; the last work-group of a
-// group reduces its partials and runs the corrector.  Partials stay within
-// 7 x (n + 4096) (small) and 7 x (2048 x 256 + n) (large) float2.  0: pairwise launches by shape, then a
-// split-reduce + corrector launch.
+// large blocks take at most kBlkBigMaxS j-ranges.  Partials stay within
+// 7 x (n + 4096) (small) and 7 x (2048 x 256 + n) (large) float2.
 #ifndef NB_BLK_STEP_FUSED
-#define NB_BLK_STEP_FUSED 0
+#define NB_BLK_STEP_FUSED 2
 #endif
 constexpr int kBlkStepWG = 256;
 constexpr int kJparIG = 2;
 constexpr int kJparJPL = 4;
-constexpr int kBlkBigMaxS = 64;
+#ifndef NB_BLK_BIG_MAXS
+#define NB_BLK_BIG_MAXS 64
+#endif
+constexpr int kBlkBigMaxS = NB_BLK_BIG_MAXS;
 constexpr int kJparItems = 2048;   // (group, range) items a small block aims for
 constexpr int kJparMaxS = 64;      // j-ranges of a small block at most
 // waves per SIMD asked of the compiler for blk_step_kernel (a register cap:
@@ -120,28 +94,7 @@ constexpr int kBlkStepWaves = NB_BLK_STEP_WAVES;
 #define NB_BLK_FRONT_FUSED 1
 #endif
 
-// Arguments of the pairwise kernel (passed by value).
-struct ForceArgs {
-    const float4* ipack;    // i records
-    const int32_t* iidx;    // i -> record index in ipack (NULL: identity)
-    int ni;
-    const float4* jpack;    // j records
-    int nj;
-    int jchunk;             // j per split (multiple of the tile)
-    float eps2;             // eps^2 rounded to float
-    int partial;            // 0: final float64 outputs, 1: write split partials
-    double G;
-    const int32_t* iself;   // self j index per i (used when self_mode == 0; NULL: none)
-    int self_mode;          // 0: iself[i], 1: iidx[i], 2: i itself
-    int keep_self;          // 1: the self pair is not masked (its i row is a copy of its j
-                            //    row, so a and jerk get exactly 0; the potential row is unused)
-    double* out[7];         // ax ay az jx jy jz pot (final mode)
-    float2* part;           // [S][7][ni] (hi, lo) partials (partial mode)
-    const DevPlan* plan;    // plan-driven launch: ni, S, jchunk come from here
-    int32_t* nn;            // nearest-neighbour evaluation: j index per i (final mode)
-    double* nn_r2;          //   and its squared distance (final mode; NULL: not wanted)
-    float2* nnpart;         //   [S][ni] (r^2, j bits) per range (partial mode)
-};
+struct ForceArgs;   // force_block.h
 
 struct ReduceArgs {
     int ni, S;
@@ -268,9 +221,11 @@ hipError_t launch_blk_front(const PackArgs& pa, const int64_t* dt, int32_t* idx,
 hipError_t launch_blk_front_fused(const PackArgs& pa, const int64_t* dt, int32_t* idx, int64_t* sel2, DevPlan* plan,
                                   uint64_t* pub, uint32_t tag, int64_t* gmin, int64_t* gmin_next, bool need_min,
                                   bool big_ok, hipStream_t st);
-// One-launch block step after the front end (NB_BLK_STEP_FUSED): pairwise sums
-// of the plan's block, split reduce and corrector.  gcnt: one counter per
-// group, zero between launches (blk_step_groups(n) words).
+// Block step after the front end (NB_BLK_STEP_FUSED): pairwise sums of the
+// plan's block in one launch for either shape; with gcnt (one counter per
+// group, zero between launches, blk_step_groups(n) words) also the split
+// reduce and the corrector, else only the sums (the plan's partials, or the
+// final forces a.out when the plan has one range).
 hipError_t launch_blk_step(int prec, bool eps0, const ForceArgs& a, const CorrectArgs& ca, unsigned* gcnt,
                            hipStream_t st);
 inline int blk_step_groups(int n) { return (n + kJparIG - 1) / kJparIG + 1; }
