@@ -427,15 +427,17 @@ int nbody_hermite_step(nbody_hermite *h, hipStream_t stream, int64_t *n_active, 
 
 /* Block steps until the next block time would exceed t_end_ticks.  With
  * block steps the block size, the launch shape and geometry of the pairwise
- * kernel (short tiles for small blocks, the large evaluations' shape from
- * 2048 particles; i-blocks, j-ranges) and the end-time gate are decided on
- * the device, by
- * one thread at the end of the selection pass; steps are enqueued in growing
- * chunks (up to 64) and the host reads the plan's statistics once per chunk
- * (so the call returns with `stream` synchronised).  A step whose
- * block time lies beyond t_end_ticks leaves the state untouched.  With
- * shared steps the block is always every particle and nothing is read
- * back. */
+ * kernel (j-parallel for blocks under 256 particles, LDS tiles above;
+ * i-groups, j-ranges) and the end-time gate are decided on the device, by
+ * the last work-group of the selection pass; steps are enqueued in growing
+ * chunks (1, 2, 4, ... up to 64) and the host reads the plan's statistics
+ * once per chunk (so the call returns with `stream` synchronised).  With
+ * the environment variable NBODY_BLOCK_GRAPH=1 set when the integrator is
+ * created, chunks of 64 steps are replayed from one captured hipGraph
+ * (captured on a context-owned stream on first use) instead of being
+ * launched step by step; the results are bit-identical.  A step whose block time lies beyond t_end_ticks
+ * leaves the state untouched.  With shared steps the block is always every
+ * particle and nothing is read back. */
 int nbody_hermite_advance(nbody_hermite *h, hipStream_t stream, int64_t t_end_ticks,
                           nbody_hermite_stats *stats);
 

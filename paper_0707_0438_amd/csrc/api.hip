@@ -128,7 +128,13 @@ struct nbody_hermite {
     uint64_t* gpub = nullptr; // block steps: per-chunk published counts of the fused front end
     unsigned* gcnt = nullptr; // block steps: per-group range counters of the one-launch step (zero between steps)
     TraceRec* ring = nullptr; // block steps: per-step records for NBODY_TRACE (device)
-    uint32_t front_tag = 0;   // tag of the last enqueued block step (never 0 once used)
+    uint32_t* ftag = nullptr; // block steps: the front end's last tag (device word after gpub)
+    // block steps replayed as a captured graph of kBlkGraphSteps steps
+    // (NBODY_BLOCK_GRAPH=1; measured slower than launching them)
+    bool use_graph = false;
+    hipGraph_t bgraph = nullptr;
+    hipGraphExec_t bexec = nullptr;
+    std::vector<uint64_t> bkey;
     int gpar = 0;             // which of the two holds this step's
     bool gmin_ok = false;     // false: recompute this step's before use
     int64_t t_ticks = 0;
@@ -809,6 +815,7 @@ int nbody_hermite_create(nbody_ctx* c, nbody_hermite** hp, int64_t n, const nbod
     h->ctx = c;
     h->n = n;
     h->o = *o;
+    if (const char* f = getenv("NBODY_BLOCK_GRAPH")) h->use_graph = atoi(f) != 0;
     const size_t nn = (size_t)n;
     // every piece below starts on a 256-byte boundary
     auto r256 = [](size_t b) { return (b + 255) & ~(size_t)255; };
@@ -817,7 +824,7 @@ int nbody_hermite_create(nbody_ctx* c, nbody_hermite** hp, int64_t n, const nbod
                          r256(sizeof(double) * 2) + r256(sizeof(DevPlan)) +
                          (o->shared_dt_log2 != 0 ? r256(sizeof(float4) * kRecDS * nn) : 0) +
                          r256(sizeof(int64_t) * blk_scratch_words((int)n)) +
-                         r256(sizeof(uint64_t) * blk_scratch_words((int)n) / 2) +
+                         r256(sizeof(uint64_t) * (blk_scratch_words((int)n) / 2 + 1)) +
                          r256(sizeof(unsigned) * blk_step_groups((int)n)) + r256(sizeof(TraceRec) * kTraceCap);
     ++c->alloc_count;
     if (c->fail_alloc_at > 0 && c->alloc_count == c->fail_alloc_at) {
@@ -848,12 +855,13 @@ int nbody_hermite_create(nbody_ctx* c, nbody_hermite** hp, int64_t n, const nbod
     h->plan = (DevPlan*)take(sizeof(DevPlan));
     if (o->shared_dt_log2 != 0) h->spack = (float4*)take(sizeof(float4) * kRecDS * nn);   // shared steps only
     h->gmin2 = (int64_t*)take(sizeof(int64_t) * blk_scratch_words((int)n));
-    h->gpub = (uint64_t*)take(sizeof(uint64_t) * blk_scratch_words((int)n) / 2);
+    h->gpub = (uint64_t*)take(sizeof(uint64_t) * (blk_scratch_words((int)n) / 2 + 1));
+    h->ftag = (uint32_t*)(h->gpub + blk_scratch_words((int)n) / 2);
     h->gcnt = (unsigned*)take(sizeof(unsigned) * blk_step_groups((int)n));
     h->ring = (TraceRec*)take(sizeof(TraceRec) * kTraceCap);
     // the published counts start untagged (tag 0 is never used); the group
     // counters start at zero
-    e = launch_fill_i64((int64_t*)h->gpub, blk_scratch_words((int)n) / 2, 0, nullptr);
+    e = launch_fill_i64((int64_t*)h->gpub, blk_scratch_words((int)n) / 2 + 1, 0, nullptr);
     if (e == hipSuccess) e = launch_fill_i32((int*)h->gcnt, blk_step_groups((int)n), 0, nullptr);
     if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
     if (e != hipSuccess) {
@@ -869,6 +877,8 @@ int nbody_hermite_destroy(nbody_hermite* h) {
     if (!h) return NBODY_OK;
     if (h->block) {
         DeviceGuard g(h->ctx->device);
+        if (h->bexec) (void)hipGraphExecDestroy(h->bexec);
+        if (h->bgraph) (void)hipGraphDestroy(h->bgraph);
         (void)hipFree(h->block);
     }
     delete h;
@@ -1120,8 +1130,7 @@ static int hermite_enqueue_block(nbody_hermite* h, hipStream_t st) {
     h->gmin_ok = false;   // until every launch of this step is in
     const bool eps0 = h->o.eps == 0.0;
 #if NB_BLK_FRONT_FUSED
-    if (++h->front_tag == 0) h->front_tag = 1;
-    hipError_t e = launch_blk_front_fused(pa, h->dt, h->idx, h->sel2, h->plan, h->gpub, h->front_tag, gmin,
+    hipError_t e = launch_blk_front_fused(pa, h->dt, h->idx, h->sel2, h->plan, h->gpub, h->ftag, gmin,
                                           gmin_next, need_min, !eps0, st);
 #else
     hipError_t e = launch_blk_front(pa, h->dt, h->idx, h->sel2, h->plan, (int64_t*)c->sel.p + 2, gmin, gmin_next,
@@ -1192,6 +1201,62 @@ static int block_buffers(nbody_hermite* h) {
 // Run block steps until the next block time would pass t_limit (or, with
 // max_steps > 0, at most that many steps); chunks of steps are enqueued
 // with one readback each.
+// With NBODY_BLOCK_GRAPH=1, once the chunk size has reached kBlkGraphSteps,
+// long runs replay the chunk from one captured hipGraph (on MI355X this
+// measured about 2 us per step slower than launching the steps, so it is
+// not the default): every launch of a block step is
+// plan-driven (sizes, shapes and the end-time gate come from device memory)
+// and its kernel arguments do not change from step to step, except the
+// kept chunk minima, which alternate between two buffers (an even step
+// count brings them back).  Captured on the context's graph stream and
+// ordered against the caller's stream by two events.
+constexpr int kBlkGraphSteps = 64;
+
+static int block_graph_launch(nbody_hermite* h, hipStream_t st) {
+    nbody_ctx* c = h->ctx;
+    hipError_t e = hipSuccess;
+    if (!c->gstream) {
+        e = hipStreamCreateWithFlags(&c->gstream, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&c->gev[0], hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&c->gev[1], hipEventDisableTiming);
+        if (e != hipSuccess) return hip_err(c, e, "graph stream setup");
+    }
+    const std::vector<uint64_t> key = {(uintptr_t)c->jpack.p, (uintptr_t)c->part.p, (uintptr_t)c->sel.p,
+                                       (uint64_t)h->gpar};
+    if (!h->bexec || h->bkey != key) {
+        if (h->bexec) (void)hipGraphExecDestroy(h->bexec);
+        if (h->bgraph) (void)hipGraphDestroy(h->bgraph);
+        h->bexec = nullptr;
+        h->bgraph = nullptr;
+        e = hipStreamBeginCapture(c->gstream, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return hip_err(c, e, "begin capture");
+        int rc = NBODY_OK;
+        for (int k = 0; k < kBlkGraphSteps && !rc; ++k) rc = hermite_enqueue_block(h, c->gstream);
+        hipGraph_t gr = nullptr;
+        const hipError_t e2 = hipStreamEndCapture(c->gstream, &gr);
+        if (rc) {
+            if (gr) (void)hipGraphDestroy(gr);
+            return rc;
+        }
+        if (e2 != hipSuccess) return hip_err(c, e2, "end capture");
+        e = hipGraphInstantiate(&h->bexec, gr, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            (void)hipGraphDestroy(gr);
+            h->bexec = nullptr;
+            return hip_err(c, e, "graph instantiate");
+        }
+        h->bgraph = gr;
+        h->bkey = key;
+    }
+    e = hipEventRecord(c->gev[0], st);
+    if (e == hipSuccess) e = hipStreamWaitEvent(c->gstream, c->gev[0], 0);
+    if (e == hipSuccess) e = hipGraphLaunch(h->bexec, c->gstream);
+    if (e == hipSuccess) e = hipEventRecord(c->gev[1], c->gstream);
+    if (e == hipSuccess) e = hipStreamWaitEvent(st, c->gev[1], 0);
+    if (e != hipSuccess) return hip_err(c, e, "graph launch");
+    return NBODY_OK;
+}
+
 static int hermite_block_run(nbody_hermite* h, hipStream_t st, int64_t t_limit, int64_t max_steps,
                              int64_t* last_nact) {
     int rc = block_buffers(h);
@@ -1202,9 +1267,14 @@ static int hermite_block_run(nbody_hermite* h, hipStream_t st, int64_t t_limit, 
     for (;;) {
         int k = chunk;
         if (max_steps > 0) k = (int)std::min<int64_t>(k, max_steps - done);
-        for (int s = 0; s < k; ++s) {
-            rc = hermite_enqueue_block(h, st);
+        if (h->use_graph && max_steps == 0 && k == kBlkGraphSteps && h->gmin_ok) {
+            rc = block_graph_launch(h, st);
             if (rc) return rc;
+        } else {
+            for (int s = 0; s < k; ++s) {
+                rc = hermite_enqueue_block(h, st);
+                if (rc) return rc;
+            }
         }
         done += k;
         DevPlan p;
@@ -1217,7 +1287,7 @@ static int hermite_block_run(nbody_hermite* h, hipStream_t st, int64_t t_limit, 
                            "block step: a wait for the chunk counts of the front end did not end");
         if (last_nact) *last_nact = p.frozen ? 0 : p.n_act;
         if (p.frozen || (max_steps > 0 && done >= max_steps)) break;
-        chunk = std::min(chunk * 2, 64);
+        chunk = std::min(chunk * 2, kBlkGraphSteps);
     }
     return NBODY_OK;
 }

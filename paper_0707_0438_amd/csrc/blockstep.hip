@@ -259,7 +259,7 @@ void blk_step_kernel(ForceArgs a, CorrectArgs ca,
 template <bool LASTWG>
 static void launch_blk_step_t(int prec, bool eps0, const ForceArgs& a, const CorrectArgs& ca, unsigned* gcnt,
                               hipStream_t st) {
-    const dim3 g(kBlkGrid), b(kBlkStepWG);
+    const dim3 g(kBlkStepGrid), b(kBlkStepWG);
     if (prec == 0) {
         if (eps0)
             hipLaunchKernelGGL((blk_step_kernel<0, true, LASTWG>), g, b, 0, st, a, ca, gcnt);

@@ -389,22 +389,28 @@ __global__ __launch_bounds__(kSelWG) void blk_write_plan_kernel(int n, int ch, i
 
 // The whole front end in one launch.  Work-group b owns chunk b: it takes
 // t_next from the kept chunk minima, counts its due particles, publishes
-// that count in pub[b] tagged with this step's number `tag`, then predicts
-// and packs its chunk, and only then waits for the counts of the chunks
-// before it to place its part of the ordered block list.  The published
-// word is the only data passed between work-groups, so it is written and
-// polled with relaxed device-scope atomics (no fences).
-// Lower-numbered work-groups are dispatched first and never wait for higher
-// ones, so every wait ends; each wait is also bounded (kFrontSpin polls),
-// after which the plan records the failure (frozen = 2) and the step does
-// nothing.  The last work-group writes the plan.  The arithmetic of the
-// count, the compaction and the pack is the same as blk_count_pack_kernel +
-// blk_write_plan_kernel, so the same block list and records come out.
+// that count in pub[b] tagged with this step's tag, then predicts and packs
+// its chunk, and only then waits for the counts of the chunks before it to
+// place its part of the ordered block list.  The published word is the only
+// data passed between work-groups, so it is written and polled with relaxed
+// device-scope atomics (no fences).  The tag is *tagp + 1 (never 0, the
+// value the words start at); the last work-group stores it back only after
+// the counts of every other work-group have arrived, each published after
+// that work-group read *tagp, so every work-group of a launch sees the same
+// tag and consecutive launches (also replays of a captured graph) never
+// share one.  Lower-numbered work-groups are dispatched first and never
+// wait for higher ones, so every wait ends; each wait is also bounded
+// (kFrontSpin polls), after which the plan records the failure (frozen = 2)
+// and the step does nothing.  A step past the end time (frozen) publishes
+// and waits as well, but packs and places nothing.  The last work-group
+// writes the plan.  The arithmetic of the count, the compaction and the pack
+// is the same as blk_count_pack_kernel + blk_write_plan_kernel, so the same
+// block list and records come out.
 template <int PREC>
 __global__ __launch_bounds__(kSelWG) void blk_front_kernel(int ch, int G, const int64_t* __restrict__ dt,
                                                            const int64_t* __restrict__ gmin,
                                                            int64_t* __restrict__ gmin_next,
-                                                           uint64_t* __restrict__ pub, uint32_t tag,
+                                                           uint64_t* __restrict__ pub, uint32_t* __restrict__ tagp,
                                                            int64_t* __restrict__ sel2, int32_t* __restrict__ idx,
                                                            DevPlan* plan, PackArgs pa, int big_ok) {
     __shared__ int64_t red[kSelWG / 64];
@@ -413,9 +419,12 @@ __global__ __launch_bounds__(kSelWG) void blk_front_kernel(int ch, int G, const 
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int b = blockIdx.x;
     const int n = pa.n;
+    uint32_t tag = *tagp + 1u;
+    tag = tag ? tag : 1u;
     int64_t m = INT64_MAX;
     for (int g = tid; g < G; g += kSelWG) m = gmin[g] < m ? gmin[g] : m;
     const int64_t tn = block_min_i64(m, red);
+    const bool frozen = tn > plan->t_limit;
     // due particles among this lane's `per` consecutive entries of the chunk
     const int per = ch / kSelWG;
     const int k0 = b * ch + tid * per;
@@ -429,6 +438,7 @@ __global__ __launch_bounds__(kSelWG) void blk_front_kernel(int ch, int G, const 
             rest = (v != tn && v < rest) ? v : rest;
         }
     }
+    if (frozen) cnt = 0;
     int incl = cnt;
     for (int off = 1; off < 64; off <<= 1) {
         const int o = __shfl_up(incl, off);
@@ -442,24 +452,14 @@ __global__ __launch_bounds__(kSelWG) void blk_front_kernel(int ch, int G, const 
         wbase += k < w ? wsum[k] : 0;
         c += wsum[k];
     }
-    const bool frozen = tn > plan->t_limit;
     if (tid == 0) {
         gmin_next[b] = frozen ? gmin[b] : rest;
         if (b == 0) sel2[1] = tn;
-        // relaxed: readers need this word's value only (no data written
-        // before it), so no release fence (an L2 write-back) is needed
         __hip_atomic_store(&pub[b], ((uint64_t)tag << 32) | (uint32_t)c, __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
     }
-    if (frozen) {
-        if (b == G - 1) {
-            sel2[0] = 0;
-            plan->n_act = 0;
-            plan->frozen = 1;
-        }
-        return;
-    }
-    for (int k = b * ch + tid; k < min(n, (b + 1) * ch); k += kSelWG) pack_one<PREC>(pa, k, tn);
+    if (!frozen)
+        for (int k = b * ch + tid; k < min(n, (b + 1) * ch); k += kSelWG) pack_one<PREC>(pa, k, tn);
     // counts of the chunks before this one
     int64_t before = 0;
     for (int g = tid; g < b; g += kSelWG) {
@@ -478,13 +478,17 @@ __global__ __launch_bounds__(kSelWG) void blk_front_kernel(int ch, int G, const 
         before += (int64_t)(uint32_t)v;
     }
     before = block_sum_i64(before, red);
-    if (fail_sh) {
-        // the step is void: no work-group waits for this one, and the host
-        // reports the failure at the end of the chunk
-        if (tid == 0) plan->frozen = 2;
-        if (b == G - 1 && tid == 0) {
+    const bool last = b == G - 1 && tid == 0;
+    if (fail_sh || frozen) {
+        // a void step (failed wait; the host reports it at the end of the
+        // chunk) or one past the end time: no block, state untouched
+        if (last) {
             sel2[0] = 0;
             plan->n_act = 0;
+            plan->frozen = fail_sh ? 2 : 1;
+            *tagp = tag;
+        } else if (fail_sh && tid == 0) {
+            plan->frozen = 2;
         }
         return;
     }
@@ -493,15 +497,16 @@ __global__ __launch_bounds__(kSelWG) void blk_front_kernel(int ch, int G, const 
         const int k = k0 + u;
         if (k < n && pa.t[k] + dt[k] == tn) idx[pos++] = k;
     }
-    if (b == G - 1 && tid == 0) {
+    if (last) {
         const int64_t total = before + c;
         sel2[0] = total;
         blk_plan_write(plan, total, tn, n, big_ok);
+        *tagp = tag;
     }
 }
 
 hipError_t launch_blk_front_fused(const PackArgs& pa, const int64_t* dt, int32_t* idx, int64_t* sel2, DevPlan* plan,
-                                  uint64_t* pub, uint32_t tag, int64_t* gmin, int64_t* gmin_next, bool need_min,
+                                  uint64_t* pub, uint32_t* tagp, int64_t* gmin, int64_t* gmin_next, bool need_min,
                                   bool big_ok, hipStream_t st) {
     const int n = pa.n;
     if (n <= 0) return hipErrorInvalidValue;
@@ -509,10 +514,10 @@ hipError_t launch_blk_front_fused(const PackArgs& pa, const int64_t* dt, int32_t
     const int G = (n + ch - 1) / ch;
     if (need_min) hipLaunchKernelGGL(blk_min_kernel, dim3(G), dim3(kSelWG), 0, st, n, ch, pa.t, dt, gmin);
     if (pa.prec == 0)
-        hipLaunchKernelGGL(blk_front_kernel<0>, dim3(G), dim3(kSelWG), 0, st, ch, G, dt, gmin, gmin_next, pub, tag,
+        hipLaunchKernelGGL(blk_front_kernel<0>, dim3(G), dim3(kSelWG), 0, st, ch, G, dt, gmin, gmin_next, pub, tagp,
                            sel2, idx, plan, pa, big_ok ? 1 : 0);
     else
-        hipLaunchKernelGGL(blk_front_kernel<1>, dim3(G), dim3(kSelWG), 0, st, ch, G, dt, gmin, gmin_next, pub, tag,
+        hipLaunchKernelGGL(blk_front_kernel<1>, dim3(G), dim3(kSelWG), 0, st, ch, G, dt, gmin, gmin_next, pub, tagp,
                            sel2, idx, plan, pa, big_ok ? 1 : 0);
     return hipGetLastError();
 }

@@ -76,13 +76,26 @@ constexpr int kBlkGrid = 2048;               // work-groups of each plan-driven 
 #endif
 constexpr int kBlkStepWG = 256;
 constexpr int kJparIG = 2;
-constexpr int kJparJPL = 4;
+#ifndef NB_JPAR_JPL
+#define NB_JPAR_JPL 2
+#endif
+constexpr int kJparJPL = NB_JPAR_JPL;
 #ifndef NB_BLK_BIG_MAXS
 #define NB_BLK_BIG_MAXS 64
 #endif
 constexpr int kBlkBigMaxS = NB_BLK_BIG_MAXS;
-constexpr int kJparItems = 2048;   // (group, range) items a small block aims for
-constexpr int kJparMaxS = 64;      // j-ranges of a small block at most
+#ifndef NB_JPAR_ITEMS
+#define NB_JPAR_ITEMS 2048
+#endif
+#ifndef NB_JPAR_MAXS
+#define NB_JPAR_MAXS 64
+#endif
+#ifndef NB_BLK_STEP_GRID
+#define NB_BLK_STEP_GRID 2048
+#endif
+constexpr int kJparItems = NB_JPAR_ITEMS;   // (group, range) items a small block aims for
+constexpr int kJparMaxS = NB_JPAR_MAXS;     // j-ranges of a small block at most
+constexpr int kBlkStepGrid = NB_BLK_STEP_GRID;   // work-groups of the block-step pairwise launch
 // waves per SIMD asked of the compiler for blk_step_kernel (a register cap:
 // the large-block tile loop keeps the occupancy of its direct-launch form)
 #ifndef NB_BLK_STEP_WAVES
@@ -216,10 +229,10 @@ hipError_t launch_blk_front(const PackArgs& pa, const int64_t* dt, int32_t* idx,
                             hipStream_t st);
 // The same front end as one launch (count, pack, ordered compaction and plan):
 // pub holds one word per chunk (zeroed once when allocated) in which each
-// step publishes its chunk counts tagged with `tag`, a number that differs
-// from step to step (never 0).
+// step publishes its chunk counts tagged with the step's tag; *tagp (zeroed
+// with pub) holds the last tag used and is advanced by the launch itself.
 hipError_t launch_blk_front_fused(const PackArgs& pa, const int64_t* dt, int32_t* idx, int64_t* sel2, DevPlan* plan,
-                                  uint64_t* pub, uint32_t tag, int64_t* gmin, int64_t* gmin_next, bool need_min,
+                                  uint64_t* pub, uint32_t* tagp, int64_t* gmin, int64_t* gmin_next, bool need_min,
                                   bool big_ok, hipStream_t st);
 // Block step after the front end (NB_BLK_STEP_FUSED): pairwise sums of the
 // plan's block in one launch for either shape; with gcnt (one counter per

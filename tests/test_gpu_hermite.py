@@ -493,3 +493,34 @@ def test_trace_lines_match_statistics(tmp_path, monkeypatch):
     assert all(b > a for a, b in zip(t, t[1:])) and t[-1] <= TICKS // 128
     assert all(r["shape"] in ("small", "large") and r["ranges"] >= 1 and r["groups"] >= 1 for r in blk)
     assert [r["t_ticks"] for r in sh] == [4096, 8192, 12288] and all(r["n_act"] == 1024 for r in sh)
+
+
+@pytest.mark.parametrize("prec", ["ds", "fp32"])
+def test_block_graph_replay_equals_eager(ctx, prec, monkeypatch):
+    """With NBODY_BLOCK_GRAPH=1 long block-step advances replay chunks of 64
+    steps from a captured hipGraph; with NBODY_BLOCK_GRAPH=0 (the default)
+    the same steps are launched one by one.  Salpeter N = 4096 to t = 1/16 (several graph replays, the last
+    one partly past the end time), then a second advance that reuses the
+    captured graph: states, block statistics and energies are
+    bit-identical."""
+    import paper_0707_0438_amd as nb
+    p = ics.plummer(4096, 4713, "salpeter")
+    eps = 1e-3
+    out = []
+    for graph in ("1", "0"):
+        monkeypatch.setenv("NBODY_BLOCK_GRAPH", graph)
+        h = ctx.hermite(p.n, eps=eps, eta=0.02, prec=prec)
+        monkeypatch.delenv("NBODY_BLOCK_GRAPH")
+        h.set_state(dev(p.pos), dev(p.vel), dev(p.mass))
+        st1 = h.advance(TICKS // 16)
+        st2 = h.advance(TICKS // 8)
+        out.append((gpu_state(h), st1, st2, h.energy()))
+        h.close()
+    (sa, a1, a2, ea), (sb, b1, b2, eb) = out
+    print(prec, "steps", a1["steps"], a2["steps"], flush=True)
+    assert a1["steps"] > 3 * 64 and a2["steps"] > a1["steps"] + 64
+    assert (a1["steps"], a1["sum_active"], a2["steps"], a2["sum_active"]) == \
+        (b1["steps"], b1["sum_active"], b2["steps"], b2["sum_active"])
+    for k in sa:
+        assert np.array_equal(sa[k], sb[k]), k
+    assert ea == eb
