@@ -126,8 +126,9 @@ struct nbody_hermite {
     int64_t spack_tn = -1;    // tick those records are valid for (-1: none)
     int64_t* gmin2 = nullptr; // block steps: two arrays of chunk minima of t + dt (this step's, next)
     uint64_t* gpub = nullptr; // block steps: per-chunk published counts of the fused front end
-    unsigned* gcnt = nullptr; // block steps: per-group range counters of the one-launch step (zero between steps)
     TraceRec* ring = nullptr; // block steps: per-step records for NBODY_TRACE (device)
+    DevPlan* splan = nullptr; // shared steps of small sets: the j-parallel plan (device; written once)
+    int splan_S = 0;          // its number of j-ranges (0: not written yet)
     uint32_t* ftag = nullptr; // block steps: the front end's last tag (device word after gpub)
     // block steps replayed as a captured graph of kBlkGraphSteps steps
     // (NBODY_BLOCK_GRAPH=1; measured slower than launching them)
@@ -821,11 +822,11 @@ int nbody_hermite_create(nbody_ctx* c, nbody_hermite** hp, int64_t n, const nbod
     auto r256 = [](size_t b) { return (b + 255) & ~(size_t)255; };
     const size_t bytes = (13 + 7 + 6) * r256(sizeof(double) * nn) + 2 * r256(sizeof(int64_t) * nn) +
                          r256(sizeof(int32_t) * nn) + r256(sizeof(int64_t) * 2) + r256(sizeof(int64_t)) +
-                         r256(sizeof(double) * 2) + r256(sizeof(DevPlan)) +
+                         r256(sizeof(double) * 2) + 2 * r256(sizeof(DevPlan)) +
                          (o->shared_dt_log2 != 0 ? r256(sizeof(float4) * kRecDS * nn) : 0) +
                          r256(sizeof(int64_t) * blk_scratch_words((int)n)) +
                          r256(sizeof(uint64_t) * (blk_scratch_words((int)n) / 2 + 1)) +
-                         r256(sizeof(unsigned) * blk_step_groups((int)n)) + r256(sizeof(TraceRec) * kTraceCap);
+                         r256(sizeof(TraceRec) * kTraceCap);
     ++c->alloc_count;
     if (c->fail_alloc_at > 0 && c->alloc_count == c->fail_alloc_at) {
         delete h;
@@ -853,16 +854,14 @@ int nbody_hermite_create(nbody_ctx* c, nbody_hermite** hp, int64_t n, const nbod
     h->tnow = (int64_t*)take(sizeof(int64_t));
     h->e2 = (double*)take(sizeof(double) * 2);
     h->plan = (DevPlan*)take(sizeof(DevPlan));
+    h->splan = (DevPlan*)take(sizeof(DevPlan));
     if (o->shared_dt_log2 != 0) h->spack = (float4*)take(sizeof(float4) * kRecDS * nn);   // shared steps only
     h->gmin2 = (int64_t*)take(sizeof(int64_t) * blk_scratch_words((int)n));
     h->gpub = (uint64_t*)take(sizeof(uint64_t) * (blk_scratch_words((int)n) / 2 + 1));
     h->ftag = (uint32_t*)(h->gpub + blk_scratch_words((int)n) / 2);
-    h->gcnt = (unsigned*)take(sizeof(unsigned) * blk_step_groups((int)n));
     h->ring = (TraceRec*)take(sizeof(TraceRec) * kTraceCap);
-    // the published counts start untagged (tag 0 is never used); the group
-    // counters start at zero
+    // the published counts start untagged (tag 0 is never used)
     e = launch_fill_i64((int64_t*)h->gpub, blk_scratch_words((int)n) / 2 + 1, 0, nullptr);
-    if (e == hipSuccess) e = launch_fill_i32((int*)h->gcnt, blk_step_groups((int)n), 0, nullptr);
     if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
     if (e != hipSuccess) {
         (void)hipFree(h->block);
@@ -1071,9 +1070,40 @@ static int hermite_step_shared(nbody_hermite* h, hipStream_t st, int64_t t_limit
     }
     const int p = (int)h->o.prec;
     int S = 1;
-    int rc = run_force(c, st, p, h->o.G, h->o.eps, n, h->spack, nullptr, nullptr, 2, n, h->spack, h->f, nullptr,
-                       0, nullptr, nullptr, &S);
-    if (rc) return rc;
+    if (n < kSharedJparMax) {
+        // small sets: the j-parallel pairwise launch of the block steps, with
+        // a plan written once from the host (the block is every particle)
+        if (!h->splan_S) {
+            DevPlan sp{};
+            sp.n_act = n;
+            sp.shape = 0;
+            jpar_plan(n, n, &sp.nb, &sp.S, &sp.jchunk);
+            int rc = dev_alloc(c, c->part, sizeof(float2) * 7 * (size_t)sp.S * (size_t)n);
+            if (rc) return rc;
+            hipError_t e = hipMemcpy(h->splan, &sp, sizeof sp, hipMemcpyHostToDevice);
+            if (e != hipSuccess) return hip_err(c, e, "plan write");
+            h->splan_S = sp.S;
+        }
+        S = h->splan_S;
+        ForceArgs a{};
+        a.ipack = h->spack;
+        a.jpack = h->spack;
+        a.ni = n;
+        a.nj = n;
+        a.eps2 = (float)(h->o.eps * h->o.eps);
+        a.G = h->o.G;
+        a.self_mode = 2;
+        a.keep_self = 1;   // each i record is its own j record: the self pair adds exactly 0 to a and jerk
+        for (int q = 0; q < 7; ++q) a.out[q] = h->f[q];
+        a.part = (float2*)c->part.p;
+        a.plan = h->splan;
+        hipError_t e = launch_blk_step(p, h->o.eps == 0.0, a, st);
+        if (e != hipSuccess) return hip_err(c, e, "force launch");
+    } else {
+        int rc = run_force(c, st, p, h->o.G, h->o.eps, n, h->spack, nullptr, nullptr, 2, n, h->spack, h->f, nullptr,
+                           0, nullptr, nullptr, &S);
+        if (rc) return rc;
+    }
     ReduceArgs r{};
     r.ni = n;
     r.S = S;
@@ -1151,19 +1181,8 @@ static int hermite_enqueue_block(nbody_hermite* h, hipStream_t st) {
     for (int q = 0; q < 7; ++q) a.out[q] = h->f[q];
     a.part = (float2*)c->part.p;
     a.plan = h->plan;
-#if NB_BLK_STEP_FUSED == 1
-    {
-        CorrectArgs ca = correct_args(h, n);
-        ca.gmin_next = gmin_next;
-        ca.gch = blk_chunk_size(n);
-        e = launch_blk_step(p, eps0, a, ca, h->gcnt, st);
-        if (e != hipSuccess) return hip_err(c, e, "block step launch");
-        h->gpar ^= 1;
-        h->gmin_ok = true;
-        return NBODY_OK;
-    }
-#elif NB_BLK_STEP_FUSED == 2
-    e = launch_blk_step(p, eps0, a, CorrectArgs{}, nullptr, st);
+#if NB_BLK_STEP_FUSED
+    e = launch_blk_step(p, eps0, a, st);
 #else
     e = launch_force_plan(p, eps0, a, st);
 #endif

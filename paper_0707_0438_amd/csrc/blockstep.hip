@@ -1,13 +1,11 @@
-// Block steps after the front end in one or two launches (Section 3.1's
-// block step, with the prediction and selection already done on the
-// device): the pairwise sums of the plan's block for either launch shape,
-// and optionally the split reduce and the corrector.
+// The pairwise launch of a block step (Section 3.1's block step, with the
+// prediction and selection already done on the device): the sums of the
+// plan's block for either launch shape, in one launch.  Shared steps of
+// small sets use it too, with a plan written by the host.
 #include "force_block.h"
 
 namespace nb {
 
-// ---- block steps: pairwise sums, split reduce and corrector in one launch ----
-//
 // Small blocks (the plan's shape 0) are j-parallel: the kJparIG i-particles
 // of a group are the same in every lane (uniform loads), and lane l of the
 // work-group takes the j records jb + l + 256 k (k < kJparJPL) of its range,
@@ -33,7 +31,7 @@ __device__ __forceinline__ void jpar_block(const ForceArgs& a, int n_act, int g,
         const int c = g * IG + k;
         float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f), r1 = r0, r2 = r0;
         if (c < n_act) {
-            const int src = a.iidx[c];
+            const int src = a.iidx ? a.iidx[c] : c;
             r0 = a.ipack[(size_t)src * R + 0];
             r1 = a.ipack[(size_t)src * R + 1];
             if (PREC == 1) r2 = a.ipack[(size_t)src * R + 2];
@@ -149,19 +147,17 @@ __device__ __forceinline__ void jpar_block(const ForceArgs& a, int n_act, int g,
     }
 }
 
-// LASTWG false: the pairwise sums only (partials, or the final forces when
-// the plan has one range); the split reduce and the corrector follow in
-// blk_reduce_correct_kernel.
-template <int PREC, bool EPS0, bool LASTWG>
+// The pairwise sums of the plan's block, either shape: the (group, range)
+// items of the plan, strided over the grid.  The split partials (or, with
+// one range, the final acceleration and jerk) go to a.part / a.out; the
+// float64 split reduce and the corrector follow in blk_reduce_correct_kernel.
+template <int PREC, bool EPS0>
 __global__ __launch_bounds__(kBlkStepWG) __attribute__((amdgpu_waves_per_eu(kBlkStepWaves)))
-void blk_step_kernel(ForceArgs a, CorrectArgs ca,
-                                                              unsigned* __restrict__ gcnt) {
+void blk_step_kernel(ForceArgs a) {
     constexpr int R = Rec<PREC>::R;
     constexpr int kTileBytes = 2 * kBlkBigTile * R * (int)sizeof(float4);
     constexpr int kRedBytes = 2 * kJparIG * 6 * kBlkStepWG * (int)sizeof(float);
     __shared__ __align__(16) unsigned char smem[kTileBytes > kRedBytes ? kTileBytes : kRedBytes];
-    __shared__ double gsum[kJparIG * 6];
-    __shared__ int last_sh;
     const DevPlan* pl = a.plan;
     const int n = (int)pl->n_act;
     if (n <= 0) return;
@@ -169,116 +165,33 @@ void blk_step_kernel(ForceArgs a, CorrectArgs ca,
     ForceArgs b = a;
     b.ni = n;
     b.jchunk = pl->jchunk;
-    b.partial = LASTWG || S > 1 ? 1 : 0;
-    const int tid = threadIdx.x;
+    b.partial = S > 1 ? 1 : 0;
     for (int v = blockIdx.x; v < nb * S; v += gridDim.x) {
         const int g = v % nb, s = v / nb;
         const int jb = s * b.jchunk;
         const int je = min(b.nj, jb + b.jchunk);
-        int gbeg, gend;
-        if (!EPS0 && shape == 1) {
+        if (!EPS0 && shape == 1)
             force_block<PREC, 1, kBlkBigTile, kBlkStepWG, false, false, 2, true>(
                 b, reinterpret_cast<float4(*)[kBlkBigTile * R]>(smem), g * kBlkStepWG, n, jb, je, b.eps2, s);
-            gbeg = g * kBlkStepWG;
-            gend = min(n, gbeg + kBlkStepWG);
-        } else {
+        else
             jpar_block<PREC, EPS0>(b, n, g, s, jb, je, reinterpret_cast<float*>(smem));
-            gbeg = g * kJparIG;
-            gend = min(n, gbeg + kJparIG);
-        }
-        if (!LASTWG) {
-            __syncthreads();   // LDS is rewritten by the next item
-            continue;
-        }
-        // This work-group's partial stores complete (work-group release and
-        // barrier), then one thread releases them device-wide (one L2
-        // write-back per work-group, no invalidation) and counts the range
-        // in.  The work-group that brings the count to S acquires (L1/L2
-        // invalidation, in that work-group only) and reads every range.
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-        __syncthreads();
-        if (tid == 0) {
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-            last_sh = __hip_atomic_fetch_add(&gcnt[g], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ==
-                      (unsigned)(S - 1);
-        }
-        __syncthreads();
-        if (last_sh) {
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-            const size_t qs = (size_t)n;
-            if (!EPS0 && shape == 1) {
-                // one thread per particle, ranges s = 0 .. S-1 in order
-                const int c = gbeg + tid;
-                if (c < gend) {
-                    double f[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-                    for (int sp = 0; sp < S; ++sp) {
-                        float2 u[6];
-#pragma unroll
-                        for (int q = 0; q < 6; ++q) u[q] = b.part[((size_t)sp * 7 + q) * qs + c];
-#pragma unroll
-                        for (int q = 0; q < 6; ++q) {
-                            f[q] += (double)u[q].x;
-                            f[q] += (double)u[q].y;
-                        }
-                    }
-#pragma unroll
-                    for (int q = 0; q < 6; ++q) f[q] *= b.G;
-                    correct_core(ca, c, f, f + 3);
-                }
-            } else {
-                // 8 threads per (particle, quantity): ranges s = part, part + 8,
-                // ... in order, then a fixed butterfly over the 8
-                if (tid < kJparIG * 6 * 8) {
-                    const int cq = tid >> 3, part = tid & 7;
-                    const int k = cq / 6, q = cq - 6 * (cq / 6);
-                    const int c = gbeg + k;
-                    double f = 0.0;
-                    if (c < gend)
-                        for (int sp = part; sp < S; sp += 8) {
-                            const float2 u = b.part[((size_t)sp * 7 + q) * qs + c];
-                            f += (double)u.x;
-                            f += (double)u.y;
-                        }
-                    f += __shfl_xor(f, 1);
-                    f += __shfl_xor(f, 2);
-                    f += __shfl_xor(f, 4);
-                    if (part == 0) gsum[cq] = b.G * f;
-                }
-                __syncthreads();
-                if (tid < kJparIG && gbeg + tid < gend) {
-                    const double* f = gsum + tid * 6;
-                    correct_core(ca, gbeg + tid, f, f + 3);
-                }
-            }
-            if (tid == 0) gcnt[g] = 0;   // ready for the next step
-        }
         __syncthreads();   // LDS is rewritten by the next item
     }
 }
 
-template <bool LASTWG>
-static void launch_blk_step_t(int prec, bool eps0, const ForceArgs& a, const CorrectArgs& ca, unsigned* gcnt,
-                              hipStream_t st) {
+hipError_t launch_blk_step(int prec, bool eps0, const ForceArgs& a, hipStream_t st) {
     const dim3 g(kBlkStepGrid), b(kBlkStepWG);
     if (prec == 0) {
         if (eps0)
-            hipLaunchKernelGGL((blk_step_kernel<0, true, LASTWG>), g, b, 0, st, a, ca, gcnt);
+            hipLaunchKernelGGL((blk_step_kernel<0, true>), g, b, 0, st, a);
         else
-            hipLaunchKernelGGL((blk_step_kernel<0, false, LASTWG>), g, b, 0, st, a, ca, gcnt);
+            hipLaunchKernelGGL((blk_step_kernel<0, false>), g, b, 0, st, a);
     } else {
         if (eps0)
-            hipLaunchKernelGGL((blk_step_kernel<1, true, LASTWG>), g, b, 0, st, a, ca, gcnt);
+            hipLaunchKernelGGL((blk_step_kernel<1, true>), g, b, 0, st, a);
         else
-            hipLaunchKernelGGL((blk_step_kernel<1, false, LASTWG>), g, b, 0, st, a, ca, gcnt);
+            hipLaunchKernelGGL((blk_step_kernel<1, false>), g, b, 0, st, a);
     }
-}
-
-hipError_t launch_blk_step(int prec, bool eps0, const ForceArgs& a, const CorrectArgs& ca, unsigned* gcnt,
-                           hipStream_t st) {
-    if (gcnt)
-        launch_blk_step_t<true>(prec, eps0, a, ca, gcnt, st);
-    else
-        launch_blk_step_t<false>(prec, eps0, a, ca, gcnt, st);
     return hipGetLastError();
 }
 

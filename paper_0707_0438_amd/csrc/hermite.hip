@@ -255,22 +255,8 @@ __device__ __forceinline__ void blk_plan_write(DevPlan* plan, int64_t total, int
 #if NB_BLK_STEP_FUSED
     if (big) {
         split_plan(total, n, kBlkStepWG, kBlkBigTile, 0, &nb, &S, &jc, 1);
-        // the one-launch form reduces a group's ranges in one work-group
-        if (NB_BLK_STEP_FUSED == 1 && S > kBlkBigMaxS)
-            split_plan(total, n, kBlkStepWG, kBlkBigTile, kBlkBigMaxS, &nb, &S, &jc, 1);
     } else {
-        // j-ranges: enough (group, range) items to spread over the device
-        // (about kJparItems), at most kJparMaxS ranges and at least one
-        // sweep of kBlkStepWG x kJparJPL records each
-        const int sweep = kBlkStepWG * kJparJPL;
-        nb = (int)((total + kJparIG - 1) / kJparIG);
-        int64_t smax = ((int64_t)n + sweep - 1) / sweep;
-        smax = smax < kJparMaxS ? smax : kJparMaxS;
-        int64_t sw = ((int64_t)kJparItems + nb - 1) / nb;
-        sw = sw < smax ? sw : smax;
-        sw = sw > 1 ? sw : 1;
-        jc = (int)((((int64_t)n + sw - 1) / sw + sweep - 1) / sweep * sweep);
-        S = (int)(((int64_t)n + jc - 1) / jc);
+        jpar_plan(total, n, &nb, &S, &jc);
     }
 #else
     if (big)

@@ -62,15 +62,14 @@ constexpr int kBlkSmallTile = NB_BLK_SMALL_TJ, kBlkSmallWG = NB_BLK_SMALL_WG;
 constexpr int kBlkBigTile = 256, kBlkBigWG = 256;
 constexpr int kBlkBigMin = NB_BLK_BIG_MIN;   // 0: the large shape is never used
 constexpr int kBlkGrid = 2048;               // work-groups of each plan-driven launch
-// Block-step launches after the front end.  0: the pairwise launches by
-// shape, then split reduce + corrector.  1: one launch (blk_step_kernel),
-// whose last work-group per i-group reduces that group's partials and runs
-// the corrector.  2: blk_step_kernel for the sums, then split reduce +
-// corrector.  In modes 1 and 2 the pairwise launch has 256-lane
-// work-groups; small blocks are j-parallel, in groups of kJparIG
-// i-particles against j-ranges swept 256 x kJparJPL records at a time;
-// large blocks take at most kBlkBigMaxS j-ranges.  Partials stay within
-// 7 x (n + 4096) (small) and 7 x (2048 x 256 + n) (large) float2.
+// Block-step launches after the front end.  2 (default): one pairwise
+// launch for either shape (blk_step_kernel, 256-lane work-groups; blocks
+// under kBlkBigMin particles j-parallel, in groups of kJparIG i-particles
+// against j-ranges swept 256 x kJparJPL records at a time; larger ones in
+// LDS tiles), then split reduce + corrector.  0: the pairwise launches by
+// shape (force_kernel_plan, two launches), then split reduce + corrector.
+// Partials stay within 7 x (n + 4096) (j-parallel) and 7 x (2048 x 256 + n)
+// (tiles) float2.
 #ifndef NB_BLK_STEP_FUSED
 #define NB_BLK_STEP_FUSED 2
 #endif
@@ -80,10 +79,6 @@ constexpr int kJparIG = 2;
 #define NB_JPAR_JPL 2
 #endif
 constexpr int kJparJPL = NB_JPAR_JPL;
-#ifndef NB_BLK_BIG_MAXS
-#define NB_BLK_BIG_MAXS 64
-#endif
-constexpr int kBlkBigMaxS = NB_BLK_BIG_MAXS;
 #ifndef NB_JPAR_ITEMS
 #define NB_JPAR_ITEMS 2048
 #endif
@@ -96,6 +91,29 @@ constexpr int kBlkBigMaxS = NB_BLK_BIG_MAXS;
 constexpr int kJparItems = NB_JPAR_ITEMS;   // (group, range) items a small block aims for
 constexpr int kJparMaxS = NB_JPAR_MAXS;     // j-ranges of a small block at most
 constexpr int kBlkStepGrid = NB_BLK_STEP_GRID;   // work-groups of the block-step pairwise launch
+// shared steps of fewer particles use the j-parallel launch as well
+#ifndef NB_SHARED_JPAR_MAX
+#define NB_SHARED_JPAR_MAX 4096
+#endif
+constexpr int kSharedJparMax = NB_SHARED_JPAR_MAX;
+// Geometry of a j-parallel pairwise launch of `total` i-particles against
+// n j-particles: nb groups of kJparIG, S j-ranges of jc records (a whole
+// number of kBlkStepWG x kJparJPL sweeps each): enough (group, range) items
+// to spread over the device (about kJparItems), at most kJparMaxS ranges.
+__host__ __device__ inline void jpar_plan(int64_t total, int n, int* nb_out, int* S_out, int* jc_out) {
+    const int sweep = kBlkStepWG * kJparJPL;
+    const int nb = (int)((total + kJparIG - 1) / kJparIG);
+    int64_t smax = ((int64_t)n + sweep - 1) / sweep;
+    smax = smax < kJparMaxS ? smax : kJparMaxS;
+    int64_t sw = ((int64_t)kJparItems + nb - 1) / nb;
+    sw = sw < smax ? sw : smax;
+    sw = sw > 1 ? sw : 1;
+    const int jc = (int)((((int64_t)n + sw - 1) / sw + sweep - 1) / sweep * sweep);
+    *nb_out = nb;
+    *jc_out = jc;
+    *S_out = (int)(((int64_t)n + jc - 1) / jc);
+}
+
 // waves per SIMD asked of the compiler for blk_step_kernel (a register cap:
 // the large-block tile loop keeps the occupancy of its direct-launch form)
 #ifndef NB_BLK_STEP_WAVES
@@ -234,14 +252,10 @@ hipError_t launch_blk_front(const PackArgs& pa, const int64_t* dt, int32_t* idx,
 hipError_t launch_blk_front_fused(const PackArgs& pa, const int64_t* dt, int32_t* idx, int64_t* sel2, DevPlan* plan,
                                   uint64_t* pub, uint32_t* tagp, int64_t* gmin, int64_t* gmin_next, bool need_min,
                                   bool big_ok, hipStream_t st);
-// Block step after the front end (NB_BLK_STEP_FUSED): pairwise sums of the
-// plan's block in one launch for either shape; with gcnt (one counter per
-// group, zero between launches, blk_step_groups(n) words) also the split
-// reduce and the corrector, else only the sums (the plan's partials, or the
-// final forces a.out when the plan has one range).
-hipError_t launch_blk_step(int prec, bool eps0, const ForceArgs& a, const CorrectArgs& ca, unsigned* gcnt,
-                           hipStream_t st);
-inline int blk_step_groups(int n) { return (n + kJparIG - 1) / kJparIG + 1; }
+// The pairwise launch of a block step (NB_BLK_STEP_FUSED): the sums of the
+// plan's block (a.plan) for either shape, as the plan's split partials
+// (a.part) or, with one range, the final acceleration and jerk (a.out).
+hipError_t launch_blk_step(int prec, bool eps0, const ForceArgs& a, hipStream_t st);
 // Block steps: split reduce (when the plan has S > 1) fused with the corrector.
 // With r.plan NULL the block is particles 0 .. r.ni-1 and the split is r.S.
 hipError_t launch_blk_reduce_correct(const ReduceArgs& r, const CorrectArgs& ca, int grid, hipStream_t st);
