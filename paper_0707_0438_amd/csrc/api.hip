@@ -129,6 +129,7 @@ struct nbody_hermite {
     TraceRec* ring = nullptr; // block steps: per-step records for NBODY_TRACE (device)
     DevPlan* splan = nullptr; // shared steps of small sets: the j-parallel plan (device; written once)
     int splan_S = 0;          // its number of j-ranges (0: not written yet)
+    bool part_checked = false; // block plans of every size checked against the partials' size
     uint32_t* ftag = nullptr; // block steps: the front end's last tag (device word after gpub)
     // block steps replayed as a captured graph of kBlkGraphSteps steps
     // (NBODY_BLOCK_GRAPH=1; measured slower than launching them)
@@ -1210,9 +1211,21 @@ static int block_buffers(nbody_hermite* h) {
     const int64_t n = h->n;
     const int words = std::max(select_scratch_words((int)n), blk_scratch_words((int)n));
     int rc = dev_alloc(c, c->sel, (2 + (size_t)words) * sizeof(int64_t));
-    // partials: S * n_act <= (2048 + nb) * per_blk <= 2049 * per_blk + n for either shape
-    const size_t per_blk = (size_t)std::max(kBlkSmallWG, kBlkBigWG);
-    if (!rc) rc = dev_alloc(c, c->part, sizeof(float2) * 7 * (2049 * per_blk + (size_t)n));
+    // split partials of a block step of any size (blk_part_rows); checked
+    // once per integrator against the plan of every block size up to 2^21
+    const int64_t rows = blk_part_rows(n, (int)h->o.prec);
+    if (!h->part_checked) {
+        const int big_ok = h->o.eps != 0.0;
+        for (int64_t tot = 1; tot <= std::min<int64_t>(n, (int64_t)1 << 21); ++tot) {
+            int nb, S, jc;
+            blk_plan_geometry(tot, (int)n, big_ok, (int)h->o.prec, &nb, &S, &jc);
+            if ((int64_t)S * tot > rows)
+                return set_err(c, NBODY_ERR_STATE, "block plan for %lld of %lld particles needs %lld partial rows > %lld",
+                               (long long)tot, (long long)n, (long long)S * tot, (long long)rows);
+        }
+        h->part_checked = true;
+    }
+    if (!rc) rc = dev_alloc(c, c->part, sizeof(float2) * 7 * (size_t)rows);
     if (!rc) rc = dev_alloc(c, c->jpack, sizeof(float4) * rec_words((int)h->o.prec) * (size_t)n);
     return rc;
 }

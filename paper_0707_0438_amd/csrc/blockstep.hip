@@ -170,9 +170,11 @@ void blk_step_kernel(ForceArgs a) {
         const int g = v % nb, s = v / nb;
         const int jb = s * b.jchunk;
         const int je = min(b.nj, jb + b.jchunk);
-        if (!EPS0 && shape == 1)
-            force_block<PREC, 1, kBlkBigTile, kBlkStepWG, false, false, 2, true>(
-                b, reinterpret_cast<float4(*)[kBlkBigTile * R]>(smem), g * kBlkStepWG, n, jb, je, b.eps2, s);
+        if (!EPS0 && shape == 1) {
+            constexpr int IPT = blk_big_ipt(PREC);
+            force_block<PREC, IPT, kBlkBigTile, kBlkStepWG, false, false, IPT == 1 ? 2 : 1, true>(
+                b, reinterpret_cast<float4(*)[kBlkBigTile * R]>(smem), g * kBlkStepWG * IPT, n, jb, je, b.eps2, s);
+        }
         else
             jpar_block<PREC, EPS0>(b, n, g, s, jb, je, reinterpret_cast<float*>(smem));
         __syncthreads();   // LDS is rewritten by the next item

@@ -217,15 +217,6 @@ hipError_t launch_select(int n, const int64_t* t, const int64_t* dt, int32_t* id
 // A step whose t_next lies beyond the plan's end time changes nothing and
 // marks the plan frozen.  Integer selection, so the block is exact.
 constexpr int kBlkGroups = 256;
-// Block steps split j down to this many tiles per range: small blocks are
-// latency-bound, so short j-ranges on many work-groups finish sooner.
-// Blocks of at most kBlkTinyMax particles (one i-block) go down to one tile
-// per range, and each work-group's sweep to a single tile.
-constexpr int kBlkMinTiles = 2;
-#ifndef NB_BLK_TINY_MAX
-#define NB_BLK_TINY_MAX 128
-#endif
-constexpr int kBlkTinyMax = NB_BLK_TINY_MAX;
 
 __host__ __device__ inline int blk_chunk(int n) {
     int ch = kSelWG;
@@ -249,21 +240,10 @@ __global__ __launch_bounds__(kSelWG) void blk_min_kernel(int n, int ch, const in
 
 constexpr int kFrontSpin = 1 << 20;
 
-__device__ __forceinline__ void blk_plan_write(DevPlan* plan, int64_t total, int64_t tn, int n, int big_ok) {
-    const int big = big_ok && kBlkBigMin > 0 && total >= kBlkBigMin;
+__device__ __forceinline__ void blk_plan_write(DevPlan* plan, int64_t total, int64_t tn, int n, int big_ok,
+                                               int prec) {
     int nb, S, jc;
-#if NB_BLK_STEP_FUSED
-    if (big) {
-        split_plan(total, n, kBlkStepWG, kBlkBigTile, 0, &nb, &S, &jc, 1);
-    } else {
-        jpar_plan(total, n, &nb, &S, &jc);
-    }
-#else
-    if (big)
-        split_plan(total, n, kBlkBigWG, kBlkBigTile, 0, &nb, &S, &jc, 1);
-    else
-        split_plan(total, n, kBlkSmallWG, kBlkSmallTile, 0, &nb, &S, &jc, total <= kBlkTinyMax ? 1 : kBlkMinTiles);
-#endif
+    const int big = blk_plan_geometry(total, n, big_ok, prec, &nb, &S, &jc);
     plan->shape = big;
     plan->n_act = total;
     plan->t_next = tn;
@@ -325,7 +305,7 @@ __global__ __launch_bounds__(kSelWG) void blk_write_plan_kernel(int n, int ch, i
                                                                 const int64_t* __restrict__ gcnt,
                                                                 int64_t* __restrict__ sel2,
                                                                 int32_t* __restrict__ idx, DevPlan* plan,
-                                                                int big_ok) {
+                                                                int big_ok, int prec) {
     __shared__ int64_t red[kSelWG / 64];
     __shared__ int wsum[kSelWG / 64];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -368,7 +348,7 @@ __global__ __launch_bounds__(kSelWG) void blk_write_plan_kernel(int n, int ch, i
             plan->frozen = 1;
         } else {
             // large blocks take the large direct evaluations' shape
-            blk_plan_write(plan, total, tn, n, big_ok);
+            blk_plan_write(plan, total, tn, n, big_ok, prec);
         }
     }
 }
@@ -486,7 +466,7 @@ __global__ __launch_bounds__(kSelWG) void blk_front_kernel(int ch, int G, const 
     if (last) {
         const int64_t total = before + c;
         sel2[0] = total;
-        blk_plan_write(plan, total, tn, n, big_ok);
+        blk_plan_write(plan, total, tn, n, big_ok, PREC);
         *tagp = tag;
     }
 }
@@ -531,7 +511,7 @@ hipError_t launch_blk_front(const PackArgs& pa, const int64_t* dt, int32_t* idx,
         hipLaunchKernelGGL(blk_count_pack_kernel<1>, dim3(G), dim3(kSelWG), 0, st, ch, G, dt, gmin, gmin_next, gcnt,
                            sel2, plan, pa);
     hipLaunchKernelGGL(blk_write_plan_kernel, dim3(G), dim3(kSelWG), 0, st, n, ch, G, pa.t, dt, gcnt, sel2, idx,
-                       plan, big_ok ? 1 : 0);
+                       plan, big_ok ? 1 : 0, pa.prec);
     return hipGetLastError();
 }
 

@@ -74,6 +74,15 @@ constexpr int kBlkGrid = 2048;               // work-groups of each plan-driven 
 #define NB_BLK_STEP_FUSED 2
 #endif
 constexpr int kBlkStepWG = 256;
+// i-particles per lane of the tile shape in the block-step launch, per
+// precision (DS, FP32)
+#ifndef NB_BLK_BIG_IPT_DS
+#define NB_BLK_BIG_IPT_DS 1
+#endif
+#ifndef NB_BLK_BIG_IPT_FP32
+#define NB_BLK_BIG_IPT_FP32 1
+#endif
+__host__ __device__ constexpr int blk_big_ipt(int prec) { return prec == 1 ? NB_BLK_BIG_IPT_DS : NB_BLK_BIG_IPT_FP32; }
 constexpr int kJparIG = 2;
 #ifndef NB_JPAR_JPL
 #define NB_JPAR_JPL 2
@@ -112,6 +121,55 @@ __host__ __device__ inline void jpar_plan(int64_t total, int n, int* nb_out, int
     *nb_out = nb;
     *jc_out = jc;
     *S_out = (int)(((int64_t)n + jc - 1) / jc);
+}
+
+// Four-launch form (NB_BLK_STEP_FUSED 0): small blocks split j down to this
+// many tiles per range (latency-bound: short j-ranges on many work-groups
+// finish sooner); blocks of at most kBlkTinyMax particles (one i-block) go
+// down to one tile per range.
+constexpr int kBlkMinTiles = 2;
+#ifndef NB_BLK_TINY_MAX
+#define NB_BLK_TINY_MAX 128
+#endif
+constexpr int kBlkTinyMax = NB_BLK_TINY_MAX;
+
+// Launch geometry of a block step of `total` particles among n: nb i-groups,
+// S j-ranges of jc records; returns the launch shape (1: LDS tiles, 0: the
+// small-block shape).  The device plan and the host's sizing of the split
+// partials (blk_part_rows) both use it.
+__host__ __device__ inline int blk_plan_geometry(int64_t total, int n, int big_ok, int prec, int* nb, int* S,
+                                                 int* jc) {
+    const int big = big_ok && kBlkBigMin > 0 && total >= kBlkBigMin;
+#if NB_BLK_STEP_FUSED
+    if (big)
+        split_plan(total, n, kBlkStepWG * blk_big_ipt(prec), kBlkBigTile, 0, nb, S, jc, 1);
+    else
+        jpar_plan(total, n, nb, S, jc);
+#else
+    (void)prec;
+    if (big)
+        split_plan(total, n, kBlkBigWG, kBlkBigTile, 0, nb, S, jc, 1);
+    else
+        split_plan(total, n, kBlkSmallWG, kBlkSmallTile, 0, nb, S, jc, total <= kBlkTinyMax ? 1 : kBlkMinTiles);
+#endif
+    return big;
+}
+
+// Rows of split partials a block step of any size among n particles may
+// write (S x n_act; each row holds 7 (hi, lo) float2).  Bound: the split
+// targets at most about 2048 (i-group, range) items, so S x nb <= 2048 + nb
+// and S x n_act <= (2048 + nb) x per-group i count, which is at most
+// 2049 x per_blk + n for the tile shapes and 4096 + kJparIG + n for the
+// j-parallel one.  (The host checks the plans of every block size against it.)
+inline int64_t blk_part_rows(int64_t n, int prec) {
+#if NB_BLK_STEP_FUSED
+    const int64_t per_blk = (int64_t)kBlkStepWG * blk_big_ipt(prec);
+#else
+    (void)prec;
+    const int64_t per_blk = kBlkSmallWG > kBlkBigWG ? kBlkSmallWG : kBlkBigWG;
+#endif
+    const int64_t tiles = 2049 * per_blk, jpar = (int64_t)(kJparItems + 1) * kJparIG;
+    return (tiles > jpar ? tiles : jpar) + n;
 }
 
 // waves per SIMD asked of the compiler for blk_step_kernel (a register cap:
