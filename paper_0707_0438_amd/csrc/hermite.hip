@@ -385,21 +385,34 @@ __global__ __launch_bounds__(kSelWG) void blk_front_kernel(int ch, int G, const 
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int b = blockIdx.x;
     const int n = pa.n;
+    // this lane's `per` consecutive entries of the chunk.  With one entry
+    // per lane (n <= kBlkGroups x kSelWG) the entry's tick, next tick and
+    // the pack's float64 inputs are loaded here, together with the chunk
+    // minima, instead of one dependent load after another.
+    const int per = ch / kSelWG;
+    const int k0 = b * ch + tid * per;
+    const bool one = per == 1;
+    int64_t t1 = 0, v1 = 0;
+    PackIn pre;
+    if (one && k0 < n) {
+        t1 = pa.t[k0];
+        v1 = t1 + dt[k0];
+        pack_load(pa, k0, true, pre);
+    }
+    const int64_t t_limit = plan->t_limit;
     uint32_t tag = *tagp + 1u;
     tag = tag ? tag : 1u;
     int64_t m = INT64_MAX;
     for (int g = tid; g < G; g += kSelWG) m = gmin[g] < m ? gmin[g] : m;
     const int64_t tn = block_min_i64(m, red);
-    const bool frozen = tn > plan->t_limit;
-    // due particles among this lane's `per` consecutive entries of the chunk
-    const int per = ch / kSelWG;
-    const int k0 = b * ch + tid * per;
+    const bool frozen = tn > t_limit;
+    // due particles among the lane's entries
     int cnt = 0;
     int64_t rest = INT64_MAX;
     for (int u = 0; u < per; ++u) {
         const int k = k0 + u;
         if (k < n) {
-            const int64_t v = pa.t[k] + dt[k];
+            const int64_t v = one ? v1 : pa.t[k] + dt[k];
             cnt += v == tn ? 1 : 0;
             rest = (v != tn && v < rest) ? v : rest;
         }
@@ -424,8 +437,13 @@ __global__ __launch_bounds__(kSelWG) void blk_front_kernel(int ch, int G, const 
         __hip_atomic_store(&pub[b], ((uint64_t)tag << 32) | (uint32_t)c, __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
     }
-    if (!frozen)
-        for (int k = b * ch + tid; k < min(n, (b + 1) * ch); k += kSelWG) pack_one<PREC>(pa, k, tn);
+    if (!frozen) {
+        if (one) {
+            if (k0 < n) pack_write<PREC>(pa, k0, pre, true, (double)(tn - t1) * kTick);
+        } else {
+            for (int k = b * ch + tid; k < min(n, (b + 1) * ch); k += kSelWG) pack_one<PREC>(pa, k, tn);
+        }
+    }
     // counts of the chunks before this one
     int64_t before = 0;
     for (int g = tid; g < b; g += kSelWG) {
@@ -461,7 +479,7 @@ __global__ __launch_bounds__(kSelWG) void blk_front_kernel(int ch, int G, const 
     int64_t pos = before + wbase + incl - cnt;
     for (int u = 0; u < per; ++u) {
         const int k = k0 + u;
-        if (k < n && pa.t[k] + dt[k] == tn) idx[pos++] = k;
+        if (k < n && (one ? v1 : pa.t[k] + dt[k]) == tn) idx[pos++] = k;
     }
     if (last) {
         const int64_t total = before + c;
@@ -564,8 +582,17 @@ __global__ __launch_bounds__(256) void blk_reduce_correct_kernel(ReduceArgs r, C
     const int tid = threadIdx.x, p = tid & 15, l = tid >> 4, w = tid >> 6;
     const int ngroups = (n + 15) / 16;
     const size_t qs = (size_t)n, rs = 7 * (size_t)n;
+    const int64_t tn = ca.tnext ? *ca.tnext : ca.tn;
     for (int g = blockIdx.x; g < ngroups; g += gridDim.x) {
         const int c = g * 16 + p;
+        // the corrector's inputs (threads 0-15, one particle each): the list
+        // entry is loaded with the partials and the state right after it, so
+        // that their latency overlaps the sums
+        const bool corr = tid < 16 && c < n;
+        int ci = 0;
+        CorrIn pre;
+        if (corr) ci = ca.idx ? ca.idx[c] : c;
+        bool pending = corr;   // (S > 1, so the first range of threads 0-15 is read below)
         double f[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
         if (c < n) {
             const float2* col = r.part + c;
@@ -576,6 +603,10 @@ __global__ __launch_bounds__(256) void blk_reduce_correct_kernel(ReduceArgs r, C
                 for (int h = 0; h < 4; ++h)
 #pragma unroll
                     for (int q = 0; q < 6; ++q) u[h][q] = col[(size_t)(sp + 16 * h) * rs + q * qs];
+                if (pending) {
+                    corr_load(ca, ci, pre);
+                    pending = false;
+                }
 #pragma unroll
                 for (int h = 0; h < 4; ++h)
 #pragma unroll
@@ -588,6 +619,10 @@ __global__ __launch_bounds__(256) void blk_reduce_correct_kernel(ReduceArgs r, C
                 float2 u[6];
 #pragma unroll
                 for (int q = 0; q < 6; ++q) u[q] = col[(size_t)sp * rs + q * qs];
+                if (pending) {
+                    corr_load(ca, ci, pre);
+                    pending = false;
+                }
 #pragma unroll
                 for (int q = 0; q < 6; ++q) {
                     f[q] += (double)u[q].x;
@@ -602,12 +637,12 @@ __global__ __launch_bounds__(256) void blk_reduce_correct_kernel(ReduceArgs r, C
             if ((tid & 63) < 16) wpart[w][p][q] = f[q];
         }
         __syncthreads();
-        if (tid < 16 && c < n) {
+        if (corr) {
             double gq[6];
 #pragma unroll
             for (int q = 0; q < 6; ++q)
                 gq[q] = r.G * (((wpart[0][p][q] + wpart[1][p][q]) + wpart[2][p][q]) + wpart[3][p][q]);
-            correct_core(ca, c, gq, gq + 3);
+            correct_apply(ca, c, ci, pre, tn, gq, gq + 3);
         }
         __syncthreads();   // wpart is rewritten by the next group
     }

@@ -390,19 +390,43 @@ __device__ __forceinline__ void predict1(double x, double v, double ac, double j
     vp = v + D * (ac + D * (0.5 * jk));
 }
 
+// The float64 inputs of particle k's j record, loaded ahead of the pack
+// (acceleration and jerk only when it predicts).
+struct PackIn {
+    double x[3], v[3], ac[3], jk[3];
+    float m;
+};
+__device__ __forceinline__ void pack_load(const PackArgs& a, int k, bool predict, PackIn& s) {
+    s.x[0] = a.x[k];
+    s.x[1] = a.y[k];
+    s.x[2] = a.z[k];
+    s.v[0] = a.vx ? a.vx[k] : 0.0;
+    s.v[1] = a.vy ? a.vy[k] : 0.0;
+    s.v[2] = a.vz ? a.vz[k] : 0.0;
+    if (predict) {
+        s.ac[0] = a.ax[k];
+        s.ac[1] = a.ay[k];
+        s.ac[2] = a.az[k];
+        s.jk[0] = a.jx[k];
+        s.jk[1] = a.jy[k];
+        s.jk[2] = a.jz[k];
+    }
+    s.m = a.m ? (float)a.m[k] : 0.f;
+}
+
 // Predict particle k over the interval D (when `predict`) and write its j
 // record: float32 position (DS: hi = fl32(x), lo = fl32(x - hi)), mass,
 // velocity.
 template <int PREC>
-__device__ __forceinline__ void pack_one_dt(const PackArgs& a, int k, bool predict, double D) {
-    double px = a.x[k], py = a.y[k], pz = a.z[k];
-    double qx = a.vx ? a.vx[k] : 0.0, qy = a.vy ? a.vy[k] : 0.0, qz = a.vz ? a.vz[k] : 0.0;
+__device__ __forceinline__ void pack_write(const PackArgs& a, int k, const PackIn& s, bool predict, double D) {
+    double px = s.x[0], py = s.x[1], pz = s.x[2];
+    double qx = s.v[0], qy = s.v[1], qz = s.v[2];
     if (predict) {
-        predict1(px, qx, a.ax[k], a.jx[k], D, px, qx);
-        predict1(py, qy, a.ay[k], a.jy[k], D, py, qy);
-        predict1(pz, qz, a.az[k], a.jz[k], D, pz, qz);
+        predict1(px, qx, s.ac[0], s.jk[0], D, px, qx);
+        predict1(py, qy, s.ac[1], s.jk[1], D, py, qy);
+        predict1(pz, qz, s.ac[2], s.jk[2], D, pz, qz);
     }
-    const float m = a.m ? (float)a.m[k] : 0.f;
+    const float m = s.m;
     if (PREC == 0) {
         a.out[2 * (size_t)k] = make_float4((float)px, (float)py, (float)pz, m);
         a.out[2 * (size_t)k + 1] = make_float4((float)qx, (float)qy, (float)qz, 0.f);
@@ -414,6 +438,13 @@ __device__ __forceinline__ void pack_one_dt(const PackArgs& a, int k, bool predi
         a.out[3 * (size_t)k + 1] = make_float4((float)qx, (float)qy, (float)qz, 0.f);
         a.out[3 * (size_t)k + 2] = make_float4(lx, ly, lz, 0.f);
     }
+}
+
+template <int PREC>
+__device__ __forceinline__ void pack_one_dt(const PackArgs& a, int k, bool predict, double D) {
+    PackIn s;
+    pack_load(a, k, predict, s);
+    pack_write<PREC>(a, k, s, predict, D);
 }
 
 // The same with the interval from the particle's tick a.t[k] to tick tn
@@ -457,26 +488,49 @@ __device__ __forceinline__ double norm3(double a, double b, double c) { return s
 //   x1 = x_p + a2 D^4/24 + a3 D^5/120,  v1 = v_p + a2 D^3/6 + a3 D^4/24,
 // then the Aarseth criterion with a2 carried to the new time, and the
 // power-of-two level rule.
-__device__ __forceinline__ void correct_core(const CorrectArgs& a, int c, const double* a1in,
-                                             const double* j1in) {
-    const int i = a.idx ? a.idx[c] : c;
-    const int64_t tn = a.tnext ? *a.tnext : a.tn;
+// The corrector's float64 inputs of particle i (its state and ticks),
+// loaded ahead of the arithmetic.
+struct CorrIn {
+    double x[3], v[3], ac[3], jk[3];
+    int64_t t, dt;
+};
+__device__ __forceinline__ void corr_load(const CorrectArgs& a, int i, CorrIn& s) {
+    s.x[0] = a.x[i];
+    s.x[1] = a.y[i];
+    s.x[2] = a.z[i];
+    s.v[0] = a.vx[i];
+    s.v[1] = a.vy[i];
+    s.v[2] = a.vz[i];
+    s.ac[0] = a.ax[i];
+    s.ac[1] = a.ay[i];
+    s.ac[2] = a.az[i];
+    s.jk[0] = a.jx[i];
+    s.jk[1] = a.jy[i];
+    s.jk[2] = a.jz[i];
+    s.t = a.t[i];
+    s.dt = a.dt[i];
+}
+
+// Correct block entry c (particle i) from its loaded inputs s and its new
+// acceleration and jerk; tn is the block time.
+__device__ __forceinline__ void correct_apply(const CorrectArgs& a, int c, int i, const CorrIn& s, int64_t tn,
+                                              const double* a1in, const double* j1in) {
     if (c == 0 && a.tnow) *a.tnow = tn;
-    const double D = (double)a.dt[i] * kTick;
+    const double D = (double)s.dt * kTick;
     double* X[3] = {a.x, a.y, a.z};
     double* V[3] = {a.vx, a.vy, a.vz};
     double* A[3] = {a.ax, a.ay, a.az};
     double* J[3] = {a.jx, a.jy, a.jz};
-    const double Dp = (double)(tn - a.t[i]) * kTick;   // equals D for an active particle
+    const double Dp = (double)(tn - s.t) * kTick;   // equals D for an active particle
     double a1[3], j1[3], a2[3], a3[3];
     const double iD = 1.0 / D, iD2 = iD * iD, iD3 = iD2 * iD;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         double xp, vp;
-        predict1(X[k][i], V[k][i], A[k][i], J[k][i], Dp, xp, vp);
+        predict1(s.x[k], s.v[k], s.ac[k], s.jk[k], Dp, xp, vp);
         a1[k] = a1in[k];
         j1[k] = j1in[k];
-        const double a0 = A[k][i], j0 = J[k][i];
+        const double a0 = s.ac[k], j0 = s.jk[k];
         const double da = a0 - a1[k];
         a2[k] = (-6.0 * da - D * (4.0 * j0 + 2.0 * j1[k])) * iD2;
         a3[k] = (12.0 * da + 6.0 * D * (j0 + j1[k])) * iD3;
@@ -508,13 +562,22 @@ __device__ __forceinline__ void correct_core(const CorrectArgs& a, int c, const 
         const double na = norm3(a1[0], a1[1], a1[2]), nj = norm3(j1[0], j1[1], j1[2]);
         const double n2 = norm3(b0, b1, b2), n3 = norm3(a3[0], a3[1], a3[2]);
         const double crit = sqrt(a.eta * (na * n2 + nj * nj) / (nj * n3 + n2 * n2));
-        const int64_t dtn = block_level(crit, a.dt[i], tn, a.lmin, a.lmax);
+        const int64_t dtn = block_level(crit, s.dt, tn, a.lmin, a.lmax);
         a.dt[i] = dtn;
         // the next block time of this particle joins its chunk's minimum
         // (ticks are non-negative, so the unsigned minimum is the minimum)
         if (a.gmin_next)
             atomicMin((unsigned long long*)&a.gmin_next[i / a.gch], (unsigned long long)(tn + dtn));
     }
+}
+
+__device__ __forceinline__ void correct_core(const CorrectArgs& a, int c, const double* a1in,
+                                             const double* j1in) {
+    const int i = a.idx ? a.idx[c] : c;
+    const int64_t tn = a.tnext ? *a.tnext : a.tn;
+    CorrIn s;
+    corr_load(a, i, s);
+    correct_apply(a, c, i, s, tn, a1in, j1in);
 }
 
 
