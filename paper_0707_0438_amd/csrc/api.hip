@@ -1194,12 +1194,13 @@ static int hermite_enqueue_block(nbody_hermite* h, hipStream_t st) {
     r.G = h->o.G;
     for (int q = 0; q < 7; ++q) r.out[q] = h->f[q];
     r.plan = h->plan;
-    // 1024 work-groups: 4096 waves for the wave-per-particle split reduce,
-    // 262144 threads for the corrector alone; both stride over larger blocks
+    // kBlkRcGrid work-groups of 256 threads, 16 particles each in the split
+    // reduce, one per thread for the corrector alone; both stride over
+    // larger blocks
     CorrectArgs ca = correct_args(h, n);
     ca.gmin_next = gmin_next;
     ca.gch = blk_chunk_size(n);
-    e = launch_blk_reduce_correct(r, ca, 1024, st);
+    e = launch_blk_reduce_correct(r, ca, kBlkRcGrid, st);
     if (e != hipSuccess) return hip_err(c, e, "reduce/corrector launch");
     h->gpar ^= 1;
     h->gmin_ok = true;

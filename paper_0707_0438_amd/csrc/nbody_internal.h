@@ -100,6 +100,10 @@ constexpr int kJparJPL = NB_JPAR_JPL;
 constexpr int kJparItems = NB_JPAR_ITEMS;   // (group, range) items a small block aims for
 constexpr int kJparMaxS = NB_JPAR_MAXS;     // j-ranges of a small block at most
 constexpr int kBlkStepGrid = NB_BLK_STEP_GRID;   // work-groups of the block-step pairwise launch
+#ifndef NB_BLK_RC_GRID
+#define NB_BLK_RC_GRID 1024
+#endif
+constexpr int kBlkRcGrid = NB_BLK_RC_GRID;       // work-groups of the block steps' reduce + corrector launch
 // shared steps of fewer particles use the j-parallel launch as well
 #ifndef NB_SHARED_JPAR_MAX
 #define NB_SHARED_JPAR_MAX 4096
@@ -133,6 +137,13 @@ constexpr int kBlkMinTiles = 2;
 #endif
 constexpr int kBlkTinyMax = NB_BLK_TINY_MAX;
 
+// (i-group, j-range) items the split of a large block aims at: 6144 (24 per
+// CU) was the fastest of 1280 ... 8192 for block steps at N = 65536
+#ifndef NB_BLK_BIG_ITEMS
+#define NB_BLK_BIG_ITEMS 6144
+#endif
+constexpr int kBlkBigItems = NB_BLK_BIG_ITEMS;
+
 // Launch geometry of a block step of `total` particles among n: nb i-groups,
 // S j-ranges of jc records; returns the launch shape (1: LDS tiles, 0: the
 // small-block shape).  The device plan and the host's sizing of the split
@@ -141,10 +152,18 @@ __host__ __device__ inline int blk_plan_geometry(int64_t total, int n, int big_o
                                                  int* jc) {
     const int big = big_ok && kBlkBigMin > 0 && total >= kBlkBigMin;
 #if NB_BLK_STEP_FUSED
-    if (big)
-        split_plan(total, n, kBlkStepWG * blk_big_ipt(prec), kBlkBigTile, 0, nb, S, jc, 1);
-    else
+    if (big) {
+        // about kBlkBigItems (i-group, j-range) items (split_plan's rule with
+        // that target)
+        const int per = kBlkStepWG * blk_big_ipt(prec);
+        const int64_t nbl = (total + per - 1) / per;
+        int64_t sr = nbl >= kBlkBigItems / 2 ? 1 : ((int64_t)kBlkBigItems + nbl - 1) / nbl;
+        const int64_t smax = n / kBlkBigTile;
+        sr = sr > smax ? smax : sr;
+        split_plan(total, n, per, kBlkBigTile, sr < 1 ? 1 : (int)sr, nb, S, jc, 1);
+    } else {
         jpar_plan(total, n, nb, S, jc);
+    }
 #else
     (void)prec;
     if (big)
@@ -157,10 +176,11 @@ __host__ __device__ inline int blk_plan_geometry(int64_t total, int n, int big_o
 
 // Rows of split partials a block step of any size among n particles may
 // write (S x n_act; each row holds 7 (hi, lo) float2).  Bound: the split
-// targets at most about 2048 (i-group, range) items, so S x nb <= 2048 + nb
-// and S x n_act <= (2048 + nb) x per-group i count, which is at most
-// 2049 x per_blk + n for the tile shapes and 4096 + kJparIG + n for the
-// j-parallel one.  (The host checks the plans of every block size against it.)
+// targets at most about T = max(kBlkBigItems, 2048) (i-group, range) items,
+// so S x nb <= T + nb and S x n_act <= (T + nb) x per-group i count, which
+// is at most (T + 1) x per_blk + n for the tile shapes and
+// (kJparItems + 1) x kJparIG + n for the j-parallel one.  (The host checks
+// the plans of every block size against it.)
 inline int64_t blk_part_rows(int64_t n, int prec) {
 #if NB_BLK_STEP_FUSED
     const int64_t per_blk = (int64_t)kBlkStepWG * blk_big_ipt(prec);
@@ -168,7 +188,8 @@ inline int64_t blk_part_rows(int64_t n, int prec) {
     (void)prec;
     const int64_t per_blk = kBlkSmallWG > kBlkBigWG ? kBlkSmallWG : kBlkBigWG;
 #endif
-    const int64_t tiles = 2049 * per_blk, jpar = (int64_t)(kJparItems + 1) * kJparIG;
+    const int64_t items = (kBlkBigItems > 2048 ? kBlkBigItems : 2048) + 1;
+    const int64_t tiles = items * per_blk, jpar = (int64_t)(kJparItems + 1) * kJparIG;
     return (tiles > jpar ? tiles : jpar) + n;
 }
 
@@ -390,6 +411,15 @@ __device__ __forceinline__ void predict1(double x, double v, double ac, double j
     vp = v + D * (ac + D * (0.5 * jk));
 }
 
+// A packed record is written with a non-temporal store: the next launch
+// reads it, from any XCD, so it gains nothing from this XCD's L2.  (Block
+// steps at N = 65536 took 1-2% less time per step than with plain stores.)
+__device__ __forceinline__ void st_rec(float4* p, float4 v) {
+    typedef float v4f __attribute__((ext_vector_type(4)));
+    const v4f w = {v.x, v.y, v.z, v.w};
+    __builtin_nontemporal_store(w, reinterpret_cast<v4f*>(p));
+}
+
 // The float64 inputs of particle k's j record, loaded ahead of the pack
 // (acceleration and jerk only when it predicts).
 struct PackIn {
@@ -428,15 +458,15 @@ __device__ __forceinline__ void pack_write(const PackArgs& a, int k, const PackI
     }
     const float m = s.m;
     if (PREC == 0) {
-        a.out[2 * (size_t)k] = make_float4((float)px, (float)py, (float)pz, m);
-        a.out[2 * (size_t)k + 1] = make_float4((float)qx, (float)qy, (float)qz, 0.f);
+        st_rec(&a.out[2 * (size_t)k], make_float4((float)px, (float)py, (float)pz, m));
+        st_rec(&a.out[2 * (size_t)k + 1], make_float4((float)qx, (float)qy, (float)qz, 0.f));
     } else {
         const float hx = (float)px, hy = (float)py, hz = (float)pz;
         const float lx = (float)(px - (double)hx), ly = (float)(py - (double)hy),
                     lz = (float)(pz - (double)hz);
-        a.out[3 * (size_t)k] = make_float4(hx, hy, hz, m);
-        a.out[3 * (size_t)k + 1] = make_float4((float)qx, (float)qy, (float)qz, 0.f);
-        a.out[3 * (size_t)k + 2] = make_float4(lx, ly, lz, 0.f);
+        st_rec(&a.out[3 * (size_t)k], make_float4(hx, hy, hz, m));
+        st_rec(&a.out[3 * (size_t)k + 1], make_float4((float)qx, (float)qy, (float)qz, 0.f));
+        st_rec(&a.out[3 * (size_t)k + 2], make_float4(lx, ly, lz, 0.f));
     }
 }
 
