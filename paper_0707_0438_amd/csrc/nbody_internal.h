@@ -95,7 +95,7 @@ constexpr int kJparJPL = NB_JPAR_JPL;
 #define NB_JPAR_MAXS 64
 #endif
 #ifndef NB_BLK_STEP_GRID
-#define NB_BLK_STEP_GRID 2048
+#define NB_BLK_STEP_GRID 6144
 #endif
 constexpr int kJparItems = NB_JPAR_ITEMS;   // (group, range) items a small block aims for
 constexpr int kJparMaxS = NB_JPAR_MAXS;     // j-ranges of a small block at most
