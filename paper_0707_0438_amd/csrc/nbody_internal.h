@@ -67,9 +67,8 @@ constexpr int kBlkGrid = 2048;               // work-groups of each plan-driven 
 // under kBlkBigMin particles j-parallel, in groups of kJparIG i-particles
 // against j-ranges swept 256 x kJparJPL records at a time; larger ones in
 // LDS tiles), then split reduce + corrector.  0: the pairwise launches by
-// shape (force_kernel_plan, two launches), then split reduce + corrector.
-// Partials stay within 7 x (n + 4096) (j-parallel) and 7 x (2048 x 256 + n)
-// (tiles) float2.
+// shape (force_kernel_plan, two launches, kBlkGrid work-groups each), then
+// split reduce + corrector.  The split partials' size: blk_part_rows.
 #ifndef NB_BLK_STEP_FUSED
 #define NB_BLK_STEP_FUSED 2
 #endif
