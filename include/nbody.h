@@ -430,7 +430,7 @@ int nbody_hermite_step(nbody_hermite *h, hipStream_t stream, int64_t *n_active, 
  * kernel (j-parallel for blocks under 256 particles, LDS tiles above;
  * i-groups, j-ranges) and the end-time gate are decided on the device, by
  * the last work-group of the selection pass; steps are enqueued in growing
- * chunks (1, 2, 4, ... up to 64) and the host reads the plan's statistics
+ * chunks (1, 2, 4, ... up to 256; 64 with NBODY_TRACE or graph replay) and the host reads the plan's statistics
  * once per chunk (so the call returns with `stream` synchronised).  With
  * the environment variable NBODY_BLOCK_GRAPH=1 set when the integrator is
  * created, chunks of 64 steps are replayed from one captured hipGraph

@@ -1244,6 +1244,14 @@ static int block_buffers(nbody_hermite* h) {
 // count brings them back).  Captured on the context's graph stream and
 // ordered against the caller's stream by two events.
 constexpr int kBlkGraphSteps = 64;
+// Launched block steps go in chunks of 1, 2, 4, ... up to this many, with
+// one plan readback (a host synchronisation) per chunk.  An advance that
+// ends inside a chunk runs its remaining steps as no-ops (the end-time
+// gate), so the chunk bounds that waste too.
+#ifndef NB_BLK_CHUNK_MAX
+#define NB_BLK_CHUNK_MAX 256
+#endif
+constexpr int kBlkChunkMax = NB_BLK_CHUNK_MAX;
 
 static int block_graph_launch(nbody_hermite* h, hipStream_t st) {
     nbody_ctx* c = h->ctx;
@@ -1320,7 +1328,10 @@ static int hermite_block_run(nbody_hermite* h, hipStream_t st, int64_t t_limit, 
                            "block step: a wait for the chunk counts of the front end did not end");
         if (last_nact) *last_nact = p.frozen ? 0 : p.n_act;
         if (p.frozen || (max_steps > 0 && done >= max_steps)) break;
-        chunk = std::min(chunk * 2, kBlkGraphSteps);
+        // chunks of launched steps grow to kBlkChunkMax; a captured graph
+        // replays kBlkGraphSteps, and the trace ring holds kTraceCap
+        const int cap = h->use_graph ? kBlkGraphSteps : trace_file(h->ctx) ? kTraceCap : kBlkChunkMax;
+        chunk = std::min(chunk * 2, cap);
     }
     return NBODY_OK;
 }
