@@ -1079,6 +1079,12 @@ static int hermite_step_shared(nbody_hermite* h, hipStream_t st, int64_t t_limit
             sp.n_act = n;
             sp.shape = 0;
             jpar_plan(n, n, &sp.nb, &sp.S, &sp.jchunk);
+            if (n <= kSharedOneRangeMax) {
+                // every group sweeps all j and writes its forces: the
+                // corrector then reads them without a split reduce
+                sp.S = 1;
+                sp.jchunk = n;
+            }
             int rc = dev_alloc(c, c->part, sizeof(float2) * 7 * (size_t)sp.S * (size_t)n);
             if (rc) return rc;
             hipError_t e = hipMemcpy(h->splan, &sp, sizeof sp, hipMemcpyHostToDevice);

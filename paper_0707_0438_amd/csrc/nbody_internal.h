@@ -82,7 +82,10 @@ constexpr int kBlkStepWG = 256;
 #define NB_BLK_BIG_IPT_FP32 1
 #endif
 __host__ __device__ constexpr int blk_big_ipt(int prec) { return prec == 1 ? NB_BLK_BIG_IPT_DS : NB_BLK_BIG_IPT_FP32; }
-constexpr int kJparIG = 2;
+#ifndef NB_JPAR_IG
+#define NB_JPAR_IG 2
+#endif
+constexpr int kJparIG = NB_JPAR_IG;   // i-particles per group of the j-parallel shape
 #ifndef NB_JPAR_JPL
 #define NB_JPAR_JPL 2
 #endif
@@ -103,6 +106,12 @@ constexpr int kBlkStepGrid = NB_BLK_STEP_GRID;   // work-groups of the block-ste
 #define NB_BLK_RC_GRID 1024
 #endif
 constexpr int kBlkRcGrid = NB_BLK_RC_GRID;       // work-groups of the block steps' reduce + corrector launch
+// shared steps of at most this many particles take one j-range (no split
+// reduce): 6-8% faster than two or more ranges at N = 1024 ... 4000
+#ifndef NB_SHARED_ONE_RANGE_MAX
+#define NB_SHARED_ONE_RANGE_MAX 4096
+#endif
+constexpr int kSharedOneRangeMax = NB_SHARED_ONE_RANGE_MAX;
 // shared steps of fewer particles use the j-parallel launch as well
 #ifndef NB_SHARED_JPAR_MAX
 #define NB_SHARED_JPAR_MAX 4096
