@@ -83,7 +83,10 @@ __global__ __launch_bounds__(kSelThreads) void select_kernel(int n, const int64_
 // reduces all group minima) and each group's count; then each group's
 // offset (sum of the counts before it) and an ordered compaction.
 constexpr int kSelChunk = 4096;
-constexpr int kSelWG = 256;
+#ifndef NB_SEL_WG
+#define NB_SEL_WG 256
+#endif
+constexpr int kSelWG = NB_SEL_WG;
 constexpr int kSelPer = kSelChunk / kSelWG;   // consecutive entries per lane
 
 __device__ __forceinline__ int64_t block_min_i64(int64_t m, int64_t* red) {
@@ -216,7 +219,10 @@ hipError_t launch_select(int n, const int64_t* t, const int64_t* dt, int32_t* id
 //      pairwise kernel, statistics.
 // A step whose t_next lies beyond the plan's end time changes nothing and
 // marks the plan frozen.  Integer selection, so the block is exact.
-constexpr int kBlkGroups = 256;
+#ifndef NB_BLK_GROUPS
+#define NB_BLK_GROUPS 256
+#endif
+constexpr int kBlkGroups = NB_BLK_GROUPS;
 
 __host__ __device__ inline int blk_chunk(int n) {
     int ch = kSelWG;
