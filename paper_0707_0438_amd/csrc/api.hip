@@ -123,7 +123,11 @@ struct nbody_hermite {
     double* e2 = nullptr;     // device [2]
     DevPlan* plan = nullptr;  // device block-step plan and statistics
     float4* spack = nullptr;  // shared steps: records of all particles predicted to spack_tn
+    float4* spack2 = nullptr; // shared steps: the next step's records while spack is being read
     int64_t spack_tn = -1;    // tick those records are valid for (-1: none)
+    // shared steps of small sets: the sums and the corrector in one launch
+    // (NBODY_FUSED_CORRECT=0: a pairwise launch and a corrector launch)
+    bool fuse = true;
     int64_t* gmin2 = nullptr; // block steps: two arrays of chunk minima of t + dt (this step's, next)
     uint64_t* gpub = nullptr; // block steps: per-chunk published counts of the fused front end
     TraceRec* ring = nullptr; // block steps: per-step records for NBODY_TRACE (device)
@@ -818,13 +822,14 @@ int nbody_hermite_create(nbody_ctx* c, nbody_hermite** hp, int64_t n, const nbod
     h->n = n;
     h->o = *o;
     if (const char* f = getenv("NBODY_BLOCK_GRAPH")) h->use_graph = atoi(f) != 0;
+    if (const char* f = getenv("NBODY_FUSED_CORRECT")) h->fuse = atoi(f) != 0;
     const size_t nn = (size_t)n;
     // every piece below starts on a 256-byte boundary
     auto r256 = [](size_t b) { return (b + 255) & ~(size_t)255; };
     const size_t bytes = (13 + 7 + 6) * r256(sizeof(double) * nn) + 2 * r256(sizeof(int64_t) * nn) +
                          r256(sizeof(int32_t) * nn) + r256(sizeof(int64_t) * 2) + r256(sizeof(int64_t)) +
                          r256(sizeof(double) * 2) + 2 * r256(sizeof(DevPlan)) +
-                         (o->shared_dt_log2 != 0 ? r256(sizeof(float4) * kRecDS * nn) : 0) +
+                         (o->shared_dt_log2 != 0 ? 2 * r256(sizeof(float4) * kRecDS * nn) : 0) +
                          r256(sizeof(int64_t) * blk_scratch_words((int)n)) +
                          r256(sizeof(uint64_t) * (blk_scratch_words((int)n) / 2 + 1)) +
                          r256(sizeof(TraceRec) * kTraceCap);
@@ -856,7 +861,10 @@ int nbody_hermite_create(nbody_ctx* c, nbody_hermite** hp, int64_t n, const nbod
     h->e2 = (double*)take(sizeof(double) * 2);
     h->plan = (DevPlan*)take(sizeof(DevPlan));
     h->splan = (DevPlan*)take(sizeof(DevPlan));
-    if (o->shared_dt_log2 != 0) h->spack = (float4*)take(sizeof(float4) * kRecDS * nn);   // shared steps only
+    if (o->shared_dt_log2 != 0) {   // shared steps only
+        h->spack = (float4*)take(sizeof(float4) * kRecDS * nn);
+        h->spack2 = (float4*)take(sizeof(float4) * kRecDS * nn);
+    }
     h->gmin2 = (int64_t*)take(sizeof(int64_t) * blk_scratch_words((int)n));
     h->gpub = (uint64_t*)take(sizeof(uint64_t) * (blk_scratch_words((int)n) / 2 + 1));
     h->ftag = (uint32_t*)(h->gpub + blk_scratch_words((int)n) / 2);
@@ -1104,6 +1112,32 @@ static int hermite_step_shared(nbody_hermite* h, hipStream_t st, int64_t t_limit
         for (int q = 0; q < 7; ++q) a.out[q] = h->f[q];
         a.part = (float2*)c->part.p;
         a.plan = h->splan;
+        if (h->fuse && S == 1 && n <= kSharedOneLaunchMax) {
+            // one launch: each work-group's group of particles gets its
+            // forces and is corrected there; the next step's records go to
+            // the second buffer, as this launch still reads the first
+            CorrectArgs ca = correct_args(h, n);
+            ca.idx = nullptr;
+            ca.tnext = nullptr;
+            ca.tn = tn;
+            ca.m = h->s[12];
+            ca.pack_next = h->spack2;
+            ca.tn_next = tn + dtk;
+            ca.pack_prec = p;
+            h->spack_tn = -1;   // until the records are swapped in below
+            hipError_t e = launch_shared_step(p, h->o.eps == 0.0, a, ca, st);
+            if (e != hipSuccess) return hip_err(c, e, "force/corrector launch");
+            std::swap(h->spack, h->spack2);
+            h->spack_tn = tn + dtk;
+            h->t_ticks = tn;
+            h->steps += 1;
+            h->sum_active += n;
+            if (trace_file(c)) {
+                trace_line(c, "shared", h->steps, tn, n, "direct", 0, S);
+                fflush(c->trace);
+            }
+            return NBODY_OK;
+        }
         hipError_t e = launch_blk_step(p, h->o.eps == 0.0, a, st);
         if (e != hipSuccess) return hip_err(c, e, "force launch");
     } else {

@@ -2,6 +2,8 @@
 // prediction and selection already done on the device): the sums of the
 // plan's block for either launch shape, in one launch.  Shared steps of
 // small sets use it too, with a plan written by the host.
+#include <algorithm>
+
 #include "force_block.h"
 
 namespace nb {
@@ -179,6 +181,50 @@ void blk_step_kernel(ForceArgs a) {
             jpar_block<PREC, EPS0>(b, n, g, s, jb, je, reinterpret_cast<float*>(smem));
         __syncthreads();   // LDS is rewritten by the next item
     }
+}
+
+// A shared step of a small set in one launch: work-group g sweeps all j for
+// the kJparIG particles of group g (the j-parallel form with one range, so
+// the group's forces are final in the work-group) and then corrects those
+// particles.  Nothing passes between work-groups: each reads the current j
+// records (a.jpack) and writes only its own particles' state and their
+// next-step records, which go to another buffer (ca.pack_next must not be
+// a.jpack).  The forces go through a.out, written and read inside the
+// work-group, so the results equal the pairwise launch with one range
+// followed by the corrector launch.
+template <int PREC, bool EPS0>
+__global__ __launch_bounds__(kBlkStepWG) void shared_step_kernel(ForceArgs a, CorrectArgs ca) {
+    __shared__ __align__(16) float smem[2 * kJparIG * 6 * kBlkStepWG];
+    const int n = a.ni;
+    const int nb = (n + kJparIG - 1) / kJparIG;
+    ForceArgs b = a;
+    b.partial = 0;
+    for (int g = blockIdx.x; g < nb; g += gridDim.x) {
+        jpar_block<PREC, EPS0>(b, n, g, 0, 0, n, smem);
+        __syncthreads();   // the group's forces are in a.out
+        const int c0 = g * kJparIG, cnt = min(kJparIG, n - c0);
+        if ((int)threadIdx.x < cnt) correct_one(ca, c0 + threadIdx.x);
+        __syncthreads();   // LDS is rewritten by the next group
+    }
+}
+
+hipError_t launch_shared_step(int prec, bool eps0, const ForceArgs& a, const CorrectArgs& ca, hipStream_t st) {
+    if (ca.pack_next && reinterpret_cast<const void*>(ca.pack_next) == reinterpret_cast<const void*>(a.jpack))
+        return hipErrorInvalidValue;
+    const int nb = (a.ni + kJparIG - 1) / kJparIG;
+    const dim3 g(std::min(nb, kBlkStepGrid)), b(kBlkStepWG);
+    if (prec == 0) {
+        if (eps0)
+            hipLaunchKernelGGL((shared_step_kernel<0, true>), g, b, 0, st, a, ca);
+        else
+            hipLaunchKernelGGL((shared_step_kernel<0, false>), g, b, 0, st, a, ca);
+    } else {
+        if (eps0)
+            hipLaunchKernelGGL((shared_step_kernel<1, true>), g, b, 0, st, a, ca);
+        else
+            hipLaunchKernelGGL((shared_step_kernel<1, false>), g, b, 0, st, a, ca);
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_blk_step(int prec, bool eps0, const ForceArgs& a, hipStream_t st) {

@@ -112,6 +112,13 @@ constexpr int kBlkRcGrid = NB_BLK_RC_GRID;       // work-groups of the block ste
 #define NB_SHARED_ONE_RANGE_MAX 4096
 #endif
 constexpr int kSharedOneRangeMax = NB_SHARED_ONE_RANGE_MAX;
+// shared steps of at most this many particles run as one launch
+// (launch_shared_step): N = 1024 DS 10.3 -> 8.4 us per step; at N = 4000 the
+// one-launch kernel's lower occupancy costs more than the launch it saves
+#ifndef NB_SHARED_ONE_LAUNCH_MAX
+#define NB_SHARED_ONE_LAUNCH_MAX 3072
+#endif
+constexpr int kSharedOneLaunchMax = NB_SHARED_ONE_LAUNCH_MAX;
 // shared steps of fewer particles use the j-parallel launch as well
 #ifndef NB_SHARED_JPAR_MAX
 #define NB_SHARED_JPAR_MAX 4096
@@ -343,6 +350,10 @@ hipError_t launch_blk_front_fused(const PackArgs& pa, const int64_t* dt, int32_t
 // plan's block (a.plan) for either shape, as the plan's split partials
 // (a.part) or, with one range, the final acceleration and jerk (a.out).
 hipError_t launch_blk_step(int prec, bool eps0, const ForceArgs& a, hipStream_t st);
+// A shared step of a.ni <= kSharedOneRangeMax particles in one launch: the
+// j-parallel sums with one range, then the corrector of each group's
+// particles in the same work-group (ca.pack_next must differ from a.jpack).
+hipError_t launch_shared_step(int prec, bool eps0, const ForceArgs& a, const CorrectArgs& ca, hipStream_t st);
 // Block steps: split reduce (when the plan has S > 1) fused with the corrector.
 // With r.plan NULL the block is particles 0 .. r.ni-1 and the split is r.S.
 hipError_t launch_blk_reduce_correct(const ReduceArgs& r, const CorrectArgs& ca, int grid, hipStream_t st);

@@ -524,3 +524,54 @@ def test_block_graph_replay_equals_eager(ctx, prec, monkeypatch):
     for k in sa:
         assert np.array_equal(sa[k], sb[k]), k
     assert ea == eb
+
+
+@pytest.mark.parametrize("prec", ["ds", "fp32"])
+def test_shared_step_one_launch_equals_two(ctx, prec, monkeypatch):
+    """Shared steps of small sets run as one launch: each work-group sweeps
+    all j for its group of particles and corrects them, writing the next
+    step's records to a second buffer.  With NBODY_FUSED_CORRECT=0 the same
+    sums (one j-range) and the same corrector run as two launches.  The
+    states and energies are bit-identical: N = 1024, a ragged N = 301, the
+    eps = 0 two-body orbit, and a run with energy evaluations and direct
+    force calls between its steps (the records alternate between the two
+    buffers)."""
+    cases = [(ics.plummer(1024, 4715), 1.0 / 256), (ics.plummer(301, 4716), 1.0 / 64)]
+    for p, eps in cases:
+        out = []
+        for fuse in ("1", "0"):
+            monkeypatch.setenv("NBODY_FUSED_CORRECT", fuse)
+            h = ctx.hermite(p.n, eps=eps, shared_dt_log2=-8, prec=prec)
+            monkeypatch.delenv("NBODY_FUSED_CORRECT")
+            X, V, M = dev(p.pos), dev(p.vel), dev(p.mass)
+            h.set_state(X, V, M)
+            st = h.advance(TICKS // 16)
+            mid = gpu_state(h)
+            for _ in range(5):
+                h.step()
+                h.energy()
+                ctx.force(X, V, X, V, M, eps, prec=prec)
+            out.append((mid, gpu_state(h), st, h.energy()))
+            h.close()
+        (ma, sa, a, ea), (mb, sb, b, eb) = out
+        print(prec, p.n, "steps", a["steps"], flush=True)
+        assert a["steps"] == b["steps"] == 16
+        for k in sa:
+            assert np.array_equal(ma[k], mb[k]), (p.n, k)
+            assert np.array_equal(sa[k], sb[k]), (p.n, k)
+        assert ea == eb
+    # eps = 0: the e = 0.5 two-body orbit
+    from test_oracle_hermite import kepler_state
+    m = np.array([0.6, 0.4])
+    x, v = kepler_state(0.6, 0.4, 1.0, 0.5, 0.0)
+    res = []
+    for fuse in ("1", "0"):
+        monkeypatch.setenv("NBODY_FUSED_CORRECT", fuse)
+        h = ctx.hermite(2, eps=0.0, shared_dt_log2=-8, prec=prec)
+        monkeypatch.delenv("NBODY_FUSED_CORRECT")
+        h.set_state(dev(x), dev(v), dev(m))
+        h.advance(TICKS // 8)
+        res.append(gpu_state(h))
+        h.close()
+    for k in res[0]:
+        assert np.array_equal(res[0][k], res[1][k]), k
