@@ -19,11 +19,12 @@ namespace nb {
 // reads.  The self pair needs no mask here: an i record is its own j record,
 // so its separation and relative velocity are exactly zero and it adds
 // exactly nothing to the acceleration and jerk (the potential is not formed).
-template <int PREC, bool EPS0>
+template <int PREC, bool EPS0, int IG = kJparIG>
 __device__ __forceinline__ void jpar_block(const ForceArgs& a, int n_act, int g, int s, int jb, int je,
                                            float* smem) {
     constexpr int R = Rec<PREC>::R;
-    constexpr int IG = kJparIG, JPL = kJparJPL, WG = kBlkStepWG;
+    constexpr int JPL = kJparJPL, WG = kBlkStepWG;
+    static_assert(IG * 6 * 8 <= WG, "the final reduce takes 8 threads per (i, quantity)");
     float* red = smem;                  // [IG * 6][WG]: high words of the lane sums
     float* losh = smem + IG * 6 * WG;   // [IG * 6][WG]: their low words
     const int tid = threadIdx.x;
@@ -194,15 +195,15 @@ void blk_step_kernel(ForceArgs a) {
 // followed by the corrector launch.
 template <int PREC, bool EPS0>
 __global__ __launch_bounds__(kBlkStepWG) void shared_step_kernel(ForceArgs a, CorrectArgs ca) {
-    __shared__ __align__(16) float smem[2 * kJparIG * 6 * kBlkStepWG];
+    __shared__ __align__(16) float smem[2 * kSharedIG * 6 * kBlkStepWG];
     const int n = a.ni;
-    const int nb = (n + kJparIG - 1) / kJparIG;
+    const int nb = (n + kSharedIG - 1) / kSharedIG;
     ForceArgs b = a;
     b.partial = 0;
     for (int g = blockIdx.x; g < nb; g += gridDim.x) {
-        jpar_block<PREC, EPS0>(b, n, g, 0, 0, n, smem);
+        jpar_block<PREC, EPS0, kSharedIG>(b, n, g, 0, 0, n, smem);
         __syncthreads();   // the group's forces are in a.out
-        const int c0 = g * kJparIG, cnt = min(kJparIG, n - c0);
+        const int c0 = g * kSharedIG, cnt = min(kSharedIG, n - c0);
         if ((int)threadIdx.x < cnt) correct_one(ca, c0 + threadIdx.x);
         __syncthreads();   // LDS is rewritten by the next group
     }
@@ -211,7 +212,7 @@ __global__ __launch_bounds__(kBlkStepWG) void shared_step_kernel(ForceArgs a, Co
 hipError_t launch_shared_step(int prec, bool eps0, const ForceArgs& a, const CorrectArgs& ca, hipStream_t st) {
     if (ca.pack_next && reinterpret_cast<const void*>(ca.pack_next) == reinterpret_cast<const void*>(a.jpack))
         return hipErrorInvalidValue;
-    const int nb = (a.ni + kJparIG - 1) / kJparIG;
+    const int nb = (a.ni + kSharedIG - 1) / kSharedIG;
     const dim3 g(std::min(nb, kBlkStepGrid)), b(kBlkStepWG);
     if (prec == 0) {
         if (eps0)

@@ -119,6 +119,11 @@ constexpr int kSharedOneRangeMax = NB_SHARED_ONE_RANGE_MAX;
 #define NB_SHARED_ONE_LAUNCH_MAX 3072
 #endif
 constexpr int kSharedOneLaunchMax = NB_SHARED_ONE_LAUNCH_MAX;
+// i-particles per work-group of the one-launch shared step
+#ifndef NB_SHARED_IG
+#define NB_SHARED_IG 2
+#endif
+constexpr int kSharedIG = NB_SHARED_IG;
 // shared steps of fewer particles use the j-parallel launch as well
 #ifndef NB_SHARED_JPAR_MAX
 #define NB_SHARED_JPAR_MAX 4096
