@@ -575,3 +575,25 @@ def test_shared_step_one_launch_equals_two(ctx, prec, monkeypatch):
         h.close()
     for k in res[0]:
         assert np.array_equal(res[0][k], res[1][k]), k
+    # one particle (a group with an empty slot, no force) and three (a full
+    # group and a partial one)
+    g = np.random.default_rng(4717)
+    for n in (1, 3):
+        x = g.standard_normal((3, n)) * 0.3
+        v = g.standard_normal((3, n)) * 0.2
+        m = np.full(n, 1.0 / n)
+        res = []
+        for fuse in ("1", "0"):
+            monkeypatch.setenv("NBODY_FUSED_CORRECT", fuse)
+            h = ctx.hermite(n, eps=0.05, shared_dt_log2=-8, prec=prec)
+            monkeypatch.delenv("NBODY_FUSED_CORRECT")
+            h.set_state(dev(x), dev(v), dev(m))
+            st = h.advance(TICKS // 16)
+            res.append((gpu_state(h), st["steps"]))
+            h.close()
+        assert res[0][1] == res[1][1] == 16
+        for k in res[0][0]:
+            assert np.array_equal(res[0][0][k], res[1][0][k]), (n, k)
+        if n == 1:
+            # no force: a straight line
+            assert np.allclose(res[0][0]["x"], x + v * (1.0 / 16), rtol=0, atol=1e-15)
