@@ -506,6 +506,59 @@ def copy_calibration(nbytes=1 << 30, reps=4):
                       "launches": reps, "GBps": round(2 * nbytes / dt / 1e9, 1)}), flush=True)
 
 
+def block_size_table(trace_csv, steps_jsonl, n_total=65536):
+    """Per-block-size time of block steps: join a rocprofv3 kernel trace
+    (CSV) of a --block-run with the NBODY_TRACE step lines of the same run.
+    The i-th traced step of each integrator is the i-th front-end launch of
+    its precision; its pairwise launch and reduce + corrector launch follow
+    it.  Launches past the last traced step (the end-time gate's no-op
+    steps) are left out.  n_total: particles of the run (for the
+    interaction rate).  Returns the table as text."""
+    import csv
+    import re
+    rows = sorted(csv.DictReader(open(trace_csv)), key=lambda r: int(r["Start_Timestamp"]))
+    lines = [json.loads(x) for x in open(steps_jsonl) if '"mode": "block"' in x]
+    runs, cur = [], []
+    for x in lines:                      # step numbers restart with each integrator
+        if cur and x["step"] <= cur[-1]["step"]:
+            runs.append(cur)
+            cur = []
+        cur.append(x)
+    if cur:
+        runs.append(cur)
+    name = lambda r: re.sub(r"\(.*", "", r["Kernel_Name"])
+    dur = lambda r: (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+    bins = [(1, 1), (2, 15), (16, 63), (64, 255), (256, 1023), (1024, 4095), (4096, 16383), (16384, 1 << 40)]
+    out = []
+    for prec, run in zip((0, 1), runs):     # the block run traces fp32 first, then ds
+        front = [r for r in rows if f"blk_front_kernel<{prec}>" in name(r)]
+        pair = [r for r in rows if f"blk_step_kernel<{prec}," in name(r)]
+        rc_all = [r for r in rows if "blk_reduce_correct" in name(r)]
+        rc, j = [], 0
+        for r in pair:                   # the reduce + corrector launch after each pairwise launch
+            t = int(r["Start_Timestamp"])
+            while j < len(rc_all) and int(rc_all[j]["Start_Timestamp"]) < t:
+                j += 1
+            rc.append(rc_all[j] if j < len(rc_all) else None)
+        acc = {b: [0, 0.0, 0.0, 0.0, 0] for b in bins}
+        for k, st in enumerate(run):
+            a = acc[next(b for b in bins if b[0] <= st["n_act"] <= b[1])]
+            a[0] += 1
+            a[1] += dur(front[k])
+            a[2] += dur(pair[k])
+            a[3] += dur(rc[k])
+            a[4] += st["n_act"]
+        out.append(f"{'fp32' if prec == 0 else 'ds'}: {len(run)} traced block steps; us per step by block size")
+        out.append(f"  {'block size':>14s} {'steps':>6s} {'front':>8s} {'pairwise':>9s} {'reduce+corr':>11s} {'pairwise Gint/s':>15s}")
+        for b in bins:
+            a = acc[b]
+            if a[0]:
+                hi = "" if b[1] >= 1 << 40 else str(b[1])
+                out.append(f"  {str(b[0]) + '-' + hi:>14s} {a[0]:6d} {a[1] / a[0]:8.2f} {a[2] / a[0]:9.2f} "
+                           f"{a[3] / a[0]:11.2f} {a[4] * n_total / a[2] / 1e3:15.1f}")
+    return "\n".join(out)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -531,7 +584,13 @@ def main():
     ap.add_argument("--no-graph", action="store_true",
                     help="launch the batched steps eagerly only (no hipGraph capture), e.g. under "
                          "profiler counter passes")
+    ap.add_argument("--block-sizes", nargs=2, metavar=("TRACE_CSV", "STEPS_JSONL"),
+                    help="only print the per-block-size times of a traced --block-run (rocprofv3 "
+                         "kernel-trace CSV, NBODY_TRACE file of the same run; its --n)")
     args = ap.parse_args()
+    if args.block_sizes:
+        print(block_size_table(*args.block_sizes, n_total=args.n if args.n != (1 << 20) else 65536), flush=True)
+        return
     if args.copy_calibration:
         copy_calibration()
         return
