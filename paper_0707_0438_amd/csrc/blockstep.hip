@@ -19,11 +19,11 @@ namespace nb {
 // reads.  The self pair needs no mask here: an i record is its own j record,
 // so its separation and relative velocity are exactly zero and it adds
 // exactly nothing to the acceleration and jerk (the potential is not formed).
-template <int PREC, bool EPS0, int IG = kJparIG>
+template <int PREC, bool EPS0, int IG = kJparIG, int JPL = kJparJPL>
 __device__ __forceinline__ void jpar_block(const ForceArgs& a, int n_act, int g, int s, int jb, int je,
                                            float* smem) {
     constexpr int R = Rec<PREC>::R;
-    constexpr int JPL = kJparJPL, WG = kBlkStepWG;
+    constexpr int WG = kBlkStepWG;
     static_assert(IG * 6 * 8 <= WG, "the final reduce takes 8 threads per (i, quantity)");
     float* red = smem;                  // [IG * 6][WG]: high words of the lane sums
     float* losh = smem + IG * 6 * WG;   // [IG * 6][WG]: their low words
@@ -193,7 +193,7 @@ void blk_step_kernel(ForceArgs a) {
 // a.jpack).  The forces go through a.out, written and read inside the
 // work-group, so the results equal the pairwise launch with one range
 // followed by the corrector launch.
-template <int PREC, bool EPS0>
+template <int PREC, bool EPS0, int JPL>
 __global__ __launch_bounds__(kBlkStepWG) void shared_step_kernel(ForceArgs a, CorrectArgs ca) {
     __shared__ __align__(16) float smem[2 * kSharedIG * 6 * kBlkStepWG];
     const int n = a.ni;
@@ -201,7 +201,7 @@ __global__ __launch_bounds__(kBlkStepWG) void shared_step_kernel(ForceArgs a, Co
     ForceArgs b = a;
     b.partial = 0;
     for (int g = blockIdx.x; g < nb; g += gridDim.x) {
-        jpar_block<PREC, EPS0, kSharedIG>(b, n, g, 0, 0, n, smem);
+        jpar_block<PREC, EPS0, kSharedIG, JPL>(b, n, g, 0, 0, n, smem);
         __syncthreads();   // the group's forces are in a.out
         const int c0 = g * kSharedIG, cnt = min(kSharedIG, n - c0);
         if ((int)threadIdx.x < cnt) correct_one(ca, c0 + threadIdx.x);
@@ -214,16 +214,24 @@ hipError_t launch_shared_step(int prec, bool eps0, const ForceArgs& a, const Cor
         return hipErrorInvalidValue;
     const int nb = (a.ni + kSharedIG - 1) / kSharedIG;
     const dim3 g(std::min(nb, kBlkStepGrid)), b(kBlkStepWG);
+    // larger sets sweep 4 records per lane (half the dependent sweeps);
+    // smaller ones keep the block steps' 2, whose sums the two-launch form
+    // repeats bit for bit
+    const bool wide = a.ni > kSharedJpl2Max;
     if (prec == 0) {
         if (eps0)
-            hipLaunchKernelGGL((shared_step_kernel<0, true>), g, b, 0, st, a, ca);
+            hipLaunchKernelGGL(wide ? (shared_step_kernel<0, true, 4>) : (shared_step_kernel<0, true, kJparJPL>), g, b,
+                               0, st, a, ca);
         else
-            hipLaunchKernelGGL((shared_step_kernel<0, false>), g, b, 0, st, a, ca);
+            hipLaunchKernelGGL(wide ? (shared_step_kernel<0, false, 4>) : (shared_step_kernel<0, false, kJparJPL>), g,
+                               b, 0, st, a, ca);
     } else {
         if (eps0)
-            hipLaunchKernelGGL((shared_step_kernel<1, true>), g, b, 0, st, a, ca);
+            hipLaunchKernelGGL(wide ? (shared_step_kernel<1, true, 4>) : (shared_step_kernel<1, true, kJparJPL>), g, b,
+                               0, st, a, ca);
         else
-            hipLaunchKernelGGL((shared_step_kernel<1, false>), g, b, 0, st, a, ca);
+            hipLaunchKernelGGL(wide ? (shared_step_kernel<1, false, 4>) : (shared_step_kernel<1, false, kJparJPL>), g,
+                               b, 0, st, a, ca);
     }
     return hipGetLastError();
 }

@@ -124,6 +124,13 @@ constexpr int kSharedOneLaunchMax = NB_SHARED_ONE_LAUNCH_MAX;
 #define NB_SHARED_IG 2
 #endif
 constexpr int kSharedIG = NB_SHARED_IG;
+// the one-launch shared step sweeps 2 j records per lane per sweep up to
+// this many particles (bit-identical to the two-launch form) and 4 above:
+// N = 2048 and 3000 6-9% faster, N = 1024 the same
+#ifndef NB_SHARED_JPL2_MAX
+#define NB_SHARED_JPL2_MAX 1536
+#endif
+constexpr int kSharedJpl2Max = NB_SHARED_JPL2_MAX;
 // shared steps of fewer particles use the j-parallel launch as well
 #ifndef NB_SHARED_JPAR_MAX
 #define NB_SHARED_JPAR_MAX 4096

@@ -597,3 +597,28 @@ def test_shared_step_one_launch_equals_two(ctx, prec, monkeypatch):
         if n == 1:
             # no force: a straight line
             assert np.allclose(res[0][0]["x"], x + v * (1.0 / 16), rtol=0, atol=1e-15)
+
+
+@pytest.mark.parametrize("prec", ["ds", "fp32"])
+def test_shared_steps_wide_sweep_against_oracle(ctx, prec):
+    """Shared steps of more than 1536 particles run the one-launch form with
+    4 j records per lane per sweep (a different float32 summation order from
+    the two-launch form).  N = 2048, eps = 1/256, 16 steps of 2^-8, against
+    the float64 oracle's run with the bars of the N = 1024 shared-step test."""
+    p = ics.plummer(2048, 4718)
+    eps = 1.0 / 256
+    ref = oracle.HermiteState(p.pos, p.vel, p.mass)
+    oracle.hermite_run(ref, TICKS // 16, eps=eps, shared_log2=-8, init=True)
+    h = ctx.hermite(p.n, eps=eps, shared_dt_log2=-8, prec=prec)
+    h.set_state(dev(p.pos), dev(p.vel), dev(p.mass))
+    st = h.advance(TICKS // 16)
+    s = gpu_state(h)
+    h.close()
+    assert st["steps"] == 16
+    dx = np.abs(s["x"] - ref.x).max()
+    dv = np.abs(s["v"] - ref.v).max()
+    print(prec, "N = 2048 max|dx|", dx, "max|dv|", dv, flush=True)
+    if prec == "ds":
+        assert dx <= 1e-7 and dv <= 1e-6
+    else:
+        assert dx <= 1e-5 and dv <= 1e-4
