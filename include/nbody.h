@@ -437,7 +437,7 @@ int nbody_hermite_step(nbody_hermite *h, hipStream_t stream, int64_t *n_active, 
  * (captured on a context-owned stream on first use) instead of being
  * launched step by step; the results are bit-identical.  A step whose block time lies beyond t_end_ticks
  * leaves the state untouched.  With shared steps the block is always every
- * particle and nothing is read back; a shared step of at most 3072
+ * particle and nothing is read back; a shared step of fewer than 4096
  * particles is one launch (each work-group gets its particles' forces and
  * corrects them), unless the environment variable NBODY_FUSED_CORRECT=0 was
  * set when the integrator was created (then a pairwise launch and a

@@ -113,10 +113,10 @@ constexpr int kBlkRcGrid = NB_BLK_RC_GRID;       // work-groups of the block ste
 #endif
 constexpr int kSharedOneRangeMax = NB_SHARED_ONE_RANGE_MAX;
 // shared steps of at most this many particles run as one launch
-// (launch_shared_step): N = 1024 DS 10.3 -> 8.4 us per step; at N = 4000 the
-// one-launch kernel's lower occupancy costs more than the launch it saves
+// (launch_shared_step): N = 1024 DS 10.3 -> 8.4 us per step, N = 4000 (with
+// four j records per lane per sweep) DS 34.5 -> 30.2 us
 #ifndef NB_SHARED_ONE_LAUNCH_MAX
-#define NB_SHARED_ONE_LAUNCH_MAX 3072
+#define NB_SHARED_ONE_LAUNCH_MAX 4096
 #endif
 constexpr int kSharedOneLaunchMax = NB_SHARED_ONE_LAUNCH_MAX;
 // i-particles per work-group of the one-launch shared step
