@@ -604,21 +604,25 @@ def test_shared_steps_wide_sweep_against_oracle(ctx, prec):
     """Shared steps of more than 1536 particles run the one-launch form with
     4 j records per lane per sweep (a different float32 summation order from
     the two-launch form).  N = 2048, eps = 1/256, 16 steps of 2^-8, against
-    the float64 oracle's run with the bars of the N = 1024 shared-step test."""
+    the float64 oracle's run with the bars of the N = 1024 shared-step test;
+    and the unsoftened instance (eps = 0) on the same set scaled by 10 (no
+    close pairs), 16 steps of 2^-6."""
     p = ics.plummer(2048, 4718)
-    eps = 1.0 / 256
-    ref = oracle.HermiteState(p.pos, p.vel, p.mass)
-    oracle.hermite_run(ref, TICKS // 16, eps=eps, shared_log2=-8, init=True)
-    h = ctx.hermite(p.n, eps=eps, shared_dt_log2=-8, prec=prec)
-    h.set_state(dev(p.pos), dev(p.vel), dev(p.mass))
-    st = h.advance(TICKS // 16)
-    s = gpu_state(h)
-    h.close()
-    assert st["steps"] == 16
-    dx = np.abs(s["x"] - ref.x).max()
-    dv = np.abs(s["v"] - ref.v).max()
-    print(prec, "N = 2048 max|dx|", dx, "max|dv|", dv, flush=True)
-    if prec == "ds":
-        assert dx <= 1e-7 and dv <= 1e-6
-    else:
-        assert dx <= 1e-5 and dv <= 1e-4
+    for eps, scale, lg in ((1.0 / 256, 1.0, -8), (0.0, 10.0, -6)):
+        x0, v0 = p.pos * scale, p.vel / np.sqrt(scale)
+        ref = oracle.HermiteState(x0, v0, p.mass)
+        T = 16 << (20 + lg)
+        oracle.hermite_run(ref, T, eps=eps, shared_log2=lg, init=True)
+        h = ctx.hermite(p.n, eps=eps, shared_dt_log2=lg, prec=prec)
+        h.set_state(dev(x0), dev(v0), dev(p.mass))
+        st = h.advance(T)
+        s = gpu_state(h)
+        h.close()
+        assert st["steps"] == 16
+        dx = np.abs(s["x"] - ref.x).max() / scale
+        dv = np.abs(s["v"] - ref.v).max() * np.sqrt(scale)
+        print(prec, "N = 2048 eps", eps, "max|dx|", dx, "max|dv|", dv, flush=True)
+        if prec == "ds":
+            assert dx <= 1e-7 and dv <= 1e-6
+        else:
+            assert dx <= 1e-5 and dv <= 1e-4
